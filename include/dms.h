@@ -1,0 +1,175 @@
+/*
+ * dms.h -- C ABI of the MI355X discrete-gradient library (libdms.so).
+ *
+ * The library computes the first step of Discrete Morse Sandwich on the
+ * Freudenthal triangulation of a 3D regular grid: the global vertex order,
+ * Robins et al.'s ProcessLowerStars discrete gradient, and the critical
+ * simplices, plus the backward scatter of the differentiable D0 form and the
+ * host-side D0 pairing that feeds it.
+ *
+ * Conventions shared by every call
+ *  - Grids are C-ordered with x fastest: vertex (i, j, k) of a grid of
+ *    dims = {nx, ny, nz} has id i + nx*(j + ny*k) ("offset in memory",
+ *    Section 2.1).  dims, lo and hi are HOST arrays of three int64 (x, y, z).
+ *  - The processed ("owned") box is the half-open [lo, hi); vertices of the
+ *    grid outside it are ghosts (Section 2.2): read, never processed.
+ *  - Array arguments are DEVICE pointers owned by the caller unless marked
+ *    [host].  Calls never allocate, free or synchronise; they enqueue work on
+ *    `stream` (a hipStream_t, NULL = the default stream) and return.
+ *  - Argument errors are returned synchronously as a dms_status and nothing
+ *    is enqueued.  Data-dependent conditions found on the device are OR-ed
+ *    into *dev_flags (a device uint32 the caller zeroes), read after a sync.
+ *  - Workspaces are caller-owned device buffers of at least the size the
+ *    matching *_workspace_size call returns; their contents on entry are
+ *    ignored.
+ */
+#ifndef DMS_H
+#define DMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DMS_OK = 0,
+    DMS_E_ARG = 1,         /* null pointer, dims < 1, box outside the grid, bad dtype */
+    DMS_E_SIZE = 2,        /* n > 2^31 - 1 vertices: int32 orders cannot rank them */
+    DMS_E_WORKSPACE = 3,   /* workspace pointer null or smaller than required */
+    DMS_E_UNSUPPORTED = 4, /* no gfx950 device current */
+    DMS_E_HIP = 5          /* a HIP runtime call (launch) failed */
+} dms_status;
+
+/* bits OR-ed into *dev_flags by the device */
+enum {
+    DMS_FLAG_NAN = 1u,      /* a NaN value: the order (and all that follows) is undefined */
+    DMS_FLAG_CAPACITY = 2u  /* a critical list exceeded its capacity; counts stay exact */
+};
+
+/* value types */
+enum { DMS_F32 = 0, DMS_F64 = 1 };
+
+/* Human-readable name of a status code (static string). */
+const char *dms_status_str(int status);
+
+/* Library version string (static). */
+const char *dms_version(void);
+
+/*
+ * Copies the library's compile-time Kuhn star tables to [host] arrays:
+ * nb[14*3] (dx, dy, dz) of each neighbour in linear-offset order,
+ * tri[36*2], tet[24*3] (neighbour indices, ascending), edge_tris[14*6]
+ * (-1 padded) and tri_tets[36*2].  Section 2.1 (Freudenthal triangulation;
+ * the diagonal +(1,1,1) is this library's reading).  Returns DMS_OK.
+ */
+int dms_star_tables(int32_t *nb, int32_t *tri, int32_t *tet, int32_t *edge_tris, int32_t *tri_tets);
+
+/* ----------------------------------------------------------------------------
+ * Global vertex order -- Section 2.1 (injectivity by pre-sorting vertices by
+ * value, ties broken by offset in memory) and Section 3 (Array
+ * Preconditioning).
+ *
+ * order[v] = number of vertices w with (f(w), w) < (f(v), v), where -0.0 and
+ * +0.0 compare equal and +-inf are ordered normally.  values: n float32
+ * (dtype DMS_F32) or float64 (DMS_F64); order: n int32.  A NaN sets
+ * DMS_FLAG_NAN and leaves order undefined.
+ * Errors: DMS_E_ARG (null pointer, n < 0, bad dtype), DMS_E_SIZE
+ * (n > 2^31 - 1), DMS_E_WORKSPACE, DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+size_t dms_order_workspace_size(int64_t n, int dtype);
+int dms_order(const void *values, int dtype, int64_t n, int32_t *order, void *workspace,
+              size_t workspace_bytes, uint32_t *dev_flags, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Discrete gradient -- Section 2.3 (discrete vectors; the gradient algorithm
+ * of Robins et al., one lower star per vertex) with the lexicographic
+ * simplex comparison of Section 2.1.
+ *
+ * For every vertex x of the box [lo, hi), pairs the cells of its lower star
+ * (x and the simplices of its star whose other vertices precede x in
+ * `order`) with Robins' ProcessLowerStars and writes one 128-bit record
+ * (four uint32, little-endian bit numbering) to rec[4 * r], r = box index
+ * with x fastest:
+ *   bits [4e, 4e+4), e = 0..13: neighbour edge e -- 0 not in L(x),
+ *     1 paired with x, 2 critical, 3+j paired with the j-th star triangle
+ *     containing e (ascending triangle index);
+ *   bits [56+2t, 58+2t), t = 0..35: star triangle t -- 0 not paired with a
+ *     tet, 1+j paired with the j-th star tet containing t.
+ * Every other cell state follows: x is critical iff all edge fields are 0; a
+ * triangle is in L(x) iff both its edges are, a head iff an edge field names
+ * it, critical if in L(x), not a head and not a tail; a tet is in L(x) iff
+ * its three edges are, critical unless a triangle field names it.
+ * order: int32 of the whole grid (dims), a permutation of 0..n-1 or any
+ * injective int32 labelling with the same relative order (values must be
+ * < 2^31 - 1).  Errors: DMS_E_ARG (null pointer, dims < 1, box outside the
+ * grid or empty is allowed and does nothing), DMS_E_SIZE, DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+int dms_discrete_gradient(const int32_t *order, const int64_t dims[3], const int64_t lo[3],
+                          const int64_t hi[3], uint32_t *rec, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Critical simplices -- Section 2.6 (zero-persistence skip: every
+ * non-critical simplex forms a zero-persistence pair with its vector
+ * partner, so only critical simplices go on) and Section 3 (Extract).
+ *
+ * Decodes the records of box [lo, hi) (as written by dms_discrete_gradient
+ * with the same dims and box) and writes, per dimension d = 0..3, the
+ * critical cells as int64 codes (max_vertex_id << 8) | local, where local is
+ * the cell's index in its max vertex's star table of that dimension (0 for
+ * the vertex itself, the neighbour edge 0..13, star triangle 0..35, star
+ * tet 0..23), listed by increasing code.  crit0..crit3: device arrays with
+ * room for cap[d] codes ([host] cap); counts: 4 device int64, always the
+ * exact totals.  When a total exceeds its capacity the list is truncated
+ * and DMS_FLAG_CAPACITY is set.
+ * Errors: DMS_E_ARG, DMS_E_SIZE, DMS_E_WORKSPACE, DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+size_t dms_critical_workspace_size(const int64_t dims[3], const int64_t lo[3], const int64_t hi[3]);
+int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3], const int64_t lo[3],
+                           const int64_t hi[3], int64_t *crit0, int64_t *crit1, int64_t *crit2,
+                           int64_t *crit3, const int64_t cap[4], int64_t *counts, void *workspace,
+                           size_t workspace_bytes, uint32_t *dev_flags, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Backward of the D0 birth/death values -- Section 2.5: a pair is embedded
+ * at (f(birth simplex), f(death simplex)) where f of a simplex is its
+ * highest vertex value, so d(birth)/d(f) and d(death)/d(f) are indicator
+ * vectors at the max vertex of each simplex.
+ *
+ * grad[v] = sum over pairs p with maxv(birth_code[p]) == v of g_birth[p]
+ *         + sum over pairs p with maxv(death_code[p]) == v of g_death[p],
+ * where maxv(code) = code >> 8.  grad (n float64) is overwritten.  Summation
+ * is deterministic: the pairs are processed so that each vertex receives its
+ * contributions in pair order when the codes of equal max vertex are
+ * adjacent (e.g. pairs listed by death code); otherwise atomic adds keep it
+ * correct up to rounding order.  Codes naming vertices outside [0, n) are ignored.
+ * Errors: DMS_E_ARG (null pointer with npairs > 0 or n > 0), DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+int dms_gradient_backward(const int64_t *birth_code, const int64_t *death_code,
+                          const double *g_birth, const double *g_death, int64_t npairs,
+                          double *grad, int64_t n, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * D0 pairing on the host -- Section 2.6 and Algorithm 1 (PairExtremaSaddles).
+ *
+ * From whole-grid records ([host] rec, 4 uint32 per vertex of dims, box =
+ * whole grid), the [host] order and the [host] list of critical edge codes,
+ * builds the extremum graph (each critical edge descends from both vertices
+ * along the vertex-edge vectors to a minimum; triplets with two distinct
+ * minima are kept), visits the triplets by increasing edge (Section 2.1
+ * comparison) and pairs each edge with the younger of its two
+ * representatives.  Writes up to `capacity` pairs to [host] pair_edge
+ * (edge codes) and pair_min (vertex ids) in processing order and their count
+ * to *npairs.  Errors: DMS_E_ARG (null pointer, code out of range),
+ * DMS_E_WORKSPACE (capacity too small: *npairs holds the count needed).
+ * -------------------------------------------------------------------------- */
+int dms_d0_pairs_host(const uint32_t *rec, const int32_t *order, const int64_t dims[3],
+                      const int64_t *crit1, int64_t n1, int64_t *pair_edge, int64_t *pair_min,
+                      int64_t capacity, int64_t *npairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMS_H */

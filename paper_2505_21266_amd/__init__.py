@@ -1,0 +1,289 @@
+"""MI355X discrete-gradient library for Discrete Morse Sandwich: Python binding.
+
+Argument marshalling only: every step runs in libdms.so (HIP kernels for
+gfx950, plus the host D0 pairing).  torch provides device memory and the
+current stream.  There is no CPU fallback: calls raise if the library is not
+built or no GPU tensor is given.
+
+Grids are torch tensors shaped (nz, ny, nx), x fastest; the library's dims
+are (nx, ny, nz).  Boxes are half-open (x, y, z) bounds [lo, hi).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdms.so")
+
+DMS_F32, DMS_F64 = 0, 1
+FLAG_NAN, FLAG_CAPACITY = 1, 2
+STATUS = {0: "DMS_OK", 1: "DMS_E_ARG", 2: "DMS_E_SIZE", 3: "DMS_E_WORKSPACE",
+          4: "DMS_E_UNSUPPORTED", 5: "DMS_E_HIP"}
+
+# every symbol include/dms.h declares
+SYMBOLS = ("dms_status_str", "dms_version", "dms_star_tables", "dms_order_workspace_size",
+           "dms_order", "dms_discrete_gradient", "dms_critical_workspace_size",
+           "dms_critical_simplices", "dms_gradient_backward", "dms_d0_pairs_host")
+
+_lib = None
+
+
+class DmsError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__("%s failed: %s" % (where, STATUS.get(status, status)))
+        self.status = status
+
+
+def lib():
+    """Loads libdms.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdms.so is not built: run __graft_entry__.build() "
+                           "(or python paper_2505_21266_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+    L.dms_status_str.argtypes = [I]
+    L.dms_status_str.restype = ctypes.c_char_p
+    L.dms_version.argtypes = []
+    L.dms_version.restype = ctypes.c_char_p
+    L.dms_star_tables.argtypes = [P, P, P, P, P]
+    L.dms_order_workspace_size.argtypes = [I64, I]
+    L.dms_order_workspace_size.restype = SZ
+    L.dms_order.argtypes = [P, I, I64, P, P, SZ, P, P]
+    L.dms_discrete_gradient.argtypes = [P, P, P, P, P, P]
+    L.dms_critical_workspace_size.argtypes = [P, P, P]
+    L.dms_critical_workspace_size.restype = SZ
+    L.dms_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
+    L.dms_gradient_backward.argtypes = [P, P, P, P, I64, P, I64, P]
+    L.dms_d0_pairs_host.argtypes = [P, P, P, P, I64, P, P, I64, P]
+    for f in ("dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_critical_simplices",
+              "dms_gradient_backward", "dms_d0_pairs_host"):
+        getattr(L, f).restype = I
+    _lib = L
+    return L
+
+
+def _check(status, where):
+    if status != 0:
+        raise DmsError(status, where)
+
+
+def _arr3(v):
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.int64).reshape(3))
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _require_gpu(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor (this library has no CPU path)" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def dims_of(t):
+    """(nx, ny, nz) of a (nz, ny, nx) tensor (1-D tensors are (n, 1, 1))."""
+    s = tuple(t.shape)
+    if len(s) == 1:
+        return (s[0], 1, 1)
+    if len(s) != 3:
+        raise ValueError("expected a 3-D (nz, ny, nx) tensor")
+    return (s[2], s[1], s[0])
+
+
+def star_tables():
+    """The library's compile-time Kuhn star tables (host copies)."""
+    L = lib()
+    nb = np.zeros((14, 3), np.int32)
+    tri = np.zeros((36, 2), np.int32)
+    tet = np.zeros((24, 3), np.int32)
+    et = np.zeros((14, 6), np.int32)
+    tt = np.zeros((36, 2), np.int32)
+    P = ctypes.c_void_p
+    _check(L.dms_star_tables(nb.ctypes.data_as(P), tri.ctypes.data_as(P), tet.ctypes.data_as(P),
+                             et.ctypes.data_as(P), tt.ctypes.data_as(P)), "dms_star_tables")
+    return dict(nb=nb, tri=tri, tet=tet, edge_tris=et, tri_tets=tt)
+
+
+class Workspace:
+    """A growable device byte buffer reused across calls."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_ws_order = Workspace()
+_ws_crit = Workspace()
+
+
+def new_flags(device):
+    import torch
+    return torch.zeros(1, dtype=torch.int32, device=device)
+
+
+def check_flags(flags, allow=0):
+    """Synchronises and raises if a device flag beyond `allow` is set."""
+    f = int(flags.item())
+    if f & ~allow & FLAG_NAN:
+        raise ValueError("NaN in the input field")
+    if f & ~allow & FLAG_CAPACITY:
+        raise RuntimeError("critical list capacity exceeded")
+    return f
+
+
+def order(values, out=None, flags=None, check=True):
+    """Global vertex order (dms_order): int32 tensor of the values' shape."""
+    import torch
+    _require_gpu(values, "values")
+    if values.dtype == torch.float32:
+        dt = DMS_F32
+    elif values.dtype == torch.float64:
+        dt = DMS_F64
+    else:
+        raise TypeError("values must be float32 or float64")
+    L = lib()
+    n = values.numel()
+    if out is None:
+        out = torch.empty(values.shape, dtype=torch.int32, device=values.device)
+    own_flags = flags is None
+    if own_flags:
+        flags = new_flags(values.device)
+    nbytes = L.dms_order_workspace_size(n, dt)
+    ws = _ws_order.get(nbytes, values.device)
+    _check(L.dms_order(_ptr(values), dt, n, _ptr(out), _ptr(ws), ws.numel(), _ptr(flags),
+                       _stream(values)), "dms_order")
+    if check and own_flags:
+        check_flags(flags)
+    return out
+
+
+def _box(dims, lo, hi):
+    lo = (0, 0, 0) if lo is None else tuple(int(v) for v in lo)
+    hi = tuple(dims) if hi is None else tuple(int(v) for v in hi)
+    return lo, hi
+
+
+def discrete_gradient(order_t, lo=None, hi=None, out=None):
+    """Lower-star records (dms_discrete_gradient): int32 tensor (nbox, 4)
+    holding the 128-bit records (reinterpret as uint32)."""
+    import torch
+    _require_gpu(order_t, "order")
+    if order_t.dtype != torch.int32:
+        raise TypeError("order must be int32")
+    dims = dims_of(order_t)
+    lo, hi = _box(dims, lo, hi)
+    nbox = max(0, (hi[0] - lo[0])) * max(0, (hi[1] - lo[1])) * max(0, (hi[2] - lo[2]))
+    if out is None:
+        out = torch.empty((nbox, 4), dtype=torch.int32, device=order_t.device)
+    d, dp = _arr3(dims)
+    l, lp = _arr3(lo)
+    h, hp = _arr3(hi)
+    _check(lib().dms_discrete_gradient(_ptr(order_t), dp, lp, hp, _ptr(out), _stream(order_t)),
+           "dms_discrete_gradient")
+    return out
+
+
+def critical_simplices(rec, dims, lo=None, hi=None, cap=None, flags=None, counts=None):
+    """Critical cells (dms_critical_simplices) as four int64 code tensors.
+
+    cap: per-dimension capacities; None sizes the lists exactly (one extra
+    counting call and a sync).  Returns (lists, counts tensor).
+    """
+    import torch
+    _require_gpu(rec, "rec")
+    dev = rec.device
+    lo, hi = _box(dims, lo, hi)
+    d, dp = _arr3(dims)
+    l, lp = _arr3(lo)
+    h, hp = _arr3(hi)
+    L = lib()
+    nbytes = L.dms_critical_workspace_size(dp, lp, hp)
+    ws = _ws_crit.get(nbytes, dev)
+    if counts is None:
+        counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    own_flags = flags is None
+    if own_flags:
+        flags = new_flags(dev)
+    st = _stream(rec)
+    if cap is None:
+        zc = np.zeros(4, np.int64)
+        _check(L.dms_critical_simplices(_ptr(rec), dp, lp, hp, None, None, None, None,
+                                        zc.ctypes.data_as(ctypes.c_void_p), _ptr(counts), _ptr(ws),
+                                        ws.numel(), _ptr(flags), st), "dms_critical_simplices")
+        cap = counts.cpu().numpy().copy()
+        flags.zero_()
+    capa = np.ascontiguousarray(np.asarray(cap, dtype=np.int64).reshape(4))
+    lists = [torch.empty(int(max(c, 0)), dtype=torch.int64, device=dev) for c in capa]
+    _check(L.dms_critical_simplices(_ptr(rec), dp, lp, hp, _ptr(lists[0]), _ptr(lists[1]),
+                                    _ptr(lists[2]), _ptr(lists[3]),
+                                    capa.ctypes.data_as(ctypes.c_void_p), _ptr(counts), _ptr(ws),
+                                    ws.numel(), _ptr(flags), st), "dms_critical_simplices")
+    if own_flags:
+        check_flags(flags)
+    return lists, counts
+
+
+def gradient_backward(birth_code, death_code, g_birth, g_death, n, out=None):
+    """dL/df from dL/d(birth, death) of D0 pairs (dms_gradient_backward)."""
+    import torch
+    for t, nm in ((birth_code, "birth_code"), (death_code, "death_code"), (g_birth, "g_birth"),
+                  (g_death, "g_death")):
+        _require_gpu(t, nm)
+    np_ = birth_code.numel()
+    if out is None:
+        out = torch.empty(int(n), dtype=torch.float64, device=birth_code.device)
+    _check(lib().dms_gradient_backward(_ptr(birth_code), _ptr(death_code), _ptr(g_birth),
+                                       _ptr(g_death), np_, _ptr(out), int(n), _stream(out)),
+           "dms_gradient_backward")
+    return out
+
+
+def d0_pairs_host(rec_np, order_np, dims, crit1_np):
+    """Host D0 pairing (dms_d0_pairs_host) on numpy arrays of the whole grid.
+    Returns (pair_edge codes, pair_min vertices) in processing order."""
+    L = lib()
+    P = ctypes.c_void_p
+    rec_np = np.ascontiguousarray(rec_np).view(np.uint32)
+    order_np = np.ascontiguousarray(order_np, dtype=np.int32)
+    crit1_np = np.ascontiguousarray(crit1_np, dtype=np.int64)
+    d, dp = _arr3(dims)
+    cap = max(int(crit1_np.size), 1)
+    pe = np.zeros(cap, np.int64)
+    pm = np.zeros(cap, np.int64)
+    npairs = np.zeros(1, np.int64)
+    _check(L.dms_d0_pairs_host(rec_np.ctypes.data_as(P), order_np.ctypes.data_as(P), dp,
+                               crit1_np.ctypes.data_as(P), crit1_np.size, pe.ctypes.data_as(P),
+                               pm.ctypes.data_as(P), cap, npairs.ctypes.data_as(P)),
+           "dms_d0_pairs_host")
+    k = int(npairs[0])
+    return pe[:k], pm[:k]
+
+
+def gradient_pipeline(values, lo=None, hi=None, cap=None):
+    """order -> discrete gradient -> critical simplices for one field."""
+    o = order(values)
+    dims = dims_of(values)
+    rec = discrete_gradient(o, lo, hi)
+    lists, counts = critical_simplices(rec, dims, lo, hi, cap=cap)
+    return o, rec, lists, counts
+
+
+from .autograd import PersistenceD0  # noqa: E402  (torch autograd wrapper)

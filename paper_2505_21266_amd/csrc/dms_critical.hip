@@ -1,0 +1,255 @@
+// dms_critical.hip -- extraction of the critical simplices from the
+// lower-star records (Section 2.6, zero-persistence skip: a cell that is
+// neither tail nor head of a discrete vector is critical; Section 3, Extract).
+//
+// Three steps over the owned box, in box order (which is vertex-id order):
+//  count  per 256-vertex tile, the number of critical cells of each dimension,
+//         from popcounts of the record fields (no table walk);
+//  scan   an exclusive scan of the 4 x ntiles tile counts;
+//  fill   per vertex, the critical cells in (dimension, local index) order,
+//         written at tile offset + block-scan offset as int64 codes
+//         (max vertex id << 8) | local index.
+#include "dms_common.hpp"
+#include "dms_scan.hpp"
+#include "dms_tables.hpp"
+
+namespace dms {
+namespace {
+
+constexpr int kThreads = 256;
+
+struct Fields {
+    uint64_t lo, hi;
+};
+
+__device__ __forceinline__ uint32_t edge_field(uint64_t lo, int e) { return (uint32_t)(lo >> (4 * e)) & 15u; }
+
+__device__ __forceinline__ uint32_t tri_field(uint64_t lo, uint64_t hi, int t)
+{
+    const int b = 56 + 2 * t;
+    return (uint32_t)((b < 64 ? lo >> b : hi >> (b - 64)) & 3u);
+}
+
+// L(x) edge mask from the edge fields
+__device__ __forceinline__ uint32_t lower_edges(uint64_t lo)
+{
+    uint32_t low = 0;
+#pragma unroll
+    for (int e = 0; e < 14; ++e) low |= (edge_field(lo, e) != 0 ? 1u : 0u) << e;
+    return low;
+}
+
+__device__ __forceinline__ uint64_t lower_tris(uint32_t low)
+{
+    uint64_t out = 0;
+#pragma unroll
+    for (int e = 0; e < 14; ++e)
+        if (!((low >> e) & 1u)) out |= kTables.edge_trimask[e];
+    return ~out & ((1ull << 36) - 1);
+}
+
+__device__ __forceinline__ uint32_t lower_tets(uint32_t low)
+{
+    uint32_t out = 0;
+#pragma unroll
+    for (int e = 0; e < 14; ++e)
+        if (!((low >> e) & 1u)) out |= kTables.edge_tetmask[e];
+    return ~out & ((1u << 24) - 1);
+}
+
+constexpr uint64_t kNib14 = 0x00ffffffffffffffull;  // 14 nibbles
+
+__device__ __forceinline__ void count_critical(uint64_t lo, uint64_t hi, uint32_t c[4])
+{
+    const uint64_t ef = lo & kNib14;
+    const uint32_t low = lower_edges(lo);
+    // fields equal to 2 (critical edges)
+    const uint64_t y = ef ^ (0x0022222222222222ull);
+    const uint64_t nz = (y | (y >> 1) | (y >> 2) | (y >> 3)) & 0x0011111111111111ull;
+    const uint32_t crit_e = 14u - (uint32_t)__popcll(nz);
+    // fields >= 3 (edges paired with a triangle: one head triangle each)
+    const uint32_t heads_t = (uint32_t)__popcll((ef + 0x0055555555555555ull) & 0x0088888888888888ull);
+    // non-zero triangle fields (triangles paired with a tet: one head tet each)
+    const uint64_t t0 = lo >> 56, t1 = hi;
+    const uint32_t tails_t = (uint32_t)__popcll((t0 | (t0 >> 1)) & 0x55ull) +
+                             (uint32_t)__popcll((t1 | (t1 >> 1)) & 0x5555555555555555ull);
+    c[0] = low == 0 ? 1u : 0u;
+    c[1] = crit_e;
+    c[2] = (uint32_t)__popcll(lower_tris(low)) - tails_t - heads_t;
+    c[3] = (uint32_t)__popc(lower_tets(low)) - tails_t;
+}
+
+__device__ __forceinline__ int64_t box_vertex(int64_t r, int64_t w0, int64_t w1, int64_t lo0,
+                                              int64_t lo1, int64_t lo2, int64_t nx, int64_t ny)
+{
+    const int64_t i = lo0 + r % w0, j = lo1 + (r / w0) % w1, k = lo2 + r / (w0 * w1);
+    return i + nx * (j + ny * k);
+}
+
+__global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec, int64_t nbox,
+                                                         uint64_t *__restrict__ tile_counts,
+                                                         int64_t ntiles)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint32_t c[4] = {0, 0, 0, 0};
+    if (r < nbox) {
+        const uint4 w = rec[r];
+        count_critical((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), c);
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        uint64_t total;
+        block_exclusive_scan<uint64_t>(c[d], &total);
+        if (threadIdx.x == 0) tile_counts[(int64_t)d * ntiles + blockIdx.x] = total;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) tile_counts[4 * ntiles] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_crit_fill(
+    const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
+    int64_t w0, int64_t w1, int64_t lo0, int64_t lo1, int64_t lo2, int64_t nx, int64_t ny,
+    int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
+    int64_t cap2, int64_t cap3)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint32_t c[4] = {0, 0, 0, 0};
+    uint64_t lo = 0, hi = 0;
+    if (r < nbox) {
+        const uint4 w = rec[r];
+        lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
+        hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
+        count_critical(lo, hi, c);
+    }
+    uint64_t at[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        uint64_t total;
+        const uint64_t ex = block_exclusive_scan<uint64_t>(c[d], &total);
+        at[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles] + ex;
+    }
+    if (r >= nbox || (c[0] | c[1] | c[2] | c[3]) == 0) return;
+    const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
+    const int64_t base = v << 8;
+    if (c[0]) {
+        if ((int64_t)at[0] < cap0) crit0[at[0]] = base;
+        return;  // a minimum has an empty lower star beyond itself
+    }
+    // full decode of this record
+    const uint32_t low = lower_edges(lo);
+    uint32_t crit_e = 0;
+    uint64_t head_t = 0, tail_t = 0;
+    uint32_t head_q = 0;
+#pragma unroll
+    for (int e = 0; e < 14; ++e) {
+        const uint32_t f = edge_field(lo, e);
+        if (f == 2) crit_e |= 1u << e;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            if (j < kTables.edge_ntri[e] && f == 3u + j) head_t |= 1ull << kTables.edge_tris[e][j];
+    }
+#pragma unroll
+    for (int t = 0; t < 36; ++t) {
+        const uint32_t g = tri_field(lo, hi, t);
+        if (g) {
+            tail_t |= 1ull << t;
+            head_q |= 1u << (g == 1 ? kTables.tri_tets[t][0] : kTables.tri_tets[t][1]);
+        }
+    }
+    const uint64_t crit_t = lower_tris(low) & ~head_t & ~tail_t;
+    const uint32_t crit_q = lower_tets(low) & ~head_q;
+    uint32_t m = crit_e;
+    int64_t a = (int64_t)at[1];
+    while (m) {
+        const int e = __ffs(m) - 1;
+        m &= m - 1;
+        if (a < cap1) crit1[a] = base | e;
+        ++a;
+    }
+    uint64_t mt = crit_t;
+    a = (int64_t)at[2];
+    while (mt) {
+        const int t = __ffsll((unsigned long long)mt) - 1;
+        mt &= mt - 1;
+        if (a < cap2) crit2[a] = base | t;
+        ++a;
+    }
+    uint32_t mq = crit_q;
+    a = (int64_t)at[3];
+    while (mq) {
+        const int q = __ffs(mq) - 1;
+        mq &= mq - 1;
+        if (a < cap3) crit3[a] = base | q;
+        ++a;
+    }
+}
+
+__global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *counts, int64_t cap0,
+                              int64_t cap1, int64_t cap2, int64_t cap3, uint32_t *flags)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t cap[4] = {cap0, cap1, cap2, cap3};
+    bool over = false;
+    for (int d = 0; d < 4; ++d) {
+        const int64_t tot = (int64_t)(offs[(int64_t)(d + 1) * ntiles] - offs[(int64_t)d * ntiles]);
+        counts[d] = tot;
+        over = over || tot > cap[d];
+    }
+    if (over) atomicOr(flags, (uint32_t)DMS_FLAG_CAPACITY);
+}
+
+__global__ void k_crit_empty(int64_t *counts)
+{
+    if (threadIdx.x < 4) counts[threadIdx.x] = 0;
+}
+
+}  // namespace
+}  // namespace dms
+
+extern "C" size_t dms_critical_workspace_size(const int64_t dims[3], const int64_t lo[3],
+                                              const int64_t hi[3])
+{
+    using namespace dms;
+    if (!box_valid(dims, lo, hi)) return 0;
+    const int64_t nbox = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+    const int64_t ntiles = (nbox + kThreads - 1) / kThreads;
+    const int64_t len = 4 * ntiles + 1;
+    return align_up((size_t)len * 8, 256) + scan_partials_bytes(len, 8);
+}
+
+extern "C" int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3], const int64_t lo[3],
+                                      const int64_t hi[3], int64_t *crit0, int64_t *crit1,
+                                      int64_t *crit2, int64_t *crit3, const int64_t cap[4],
+                                      int64_t *counts, void *workspace, size_t workspace_bytes,
+                                      uint32_t *dev_flags, void *stream)
+{
+    using namespace dms;
+    if (!box_valid(dims, lo, hi) || !cap || !counts || !dev_flags) return DMS_E_ARG;
+    if (!grid_size_ok(dims)) return DMS_E_SIZE;
+    for (int d = 0; d < 4; ++d)
+        if (cap[d] < 0) return DMS_E_ARG;
+    if ((cap[0] && !crit0) || (cap[1] && !crit1) || (cap[2] && !crit2) || (cap[3] && !crit3))
+        return DMS_E_ARG;
+    const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
+    const int64_t nbox = w0 * w1 * w2;
+    if (nbox > 0 && !rec) return DMS_E_ARG;
+    const size_t need = dms_critical_workspace_size(dims, lo, hi);
+    if (!workspace || workspace_bytes < need) return DMS_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ntiles = (nbox + kThreads - 1) / kThreads;
+    const int64_t len = 4 * ntiles + 1;
+    uint64_t *tc = (uint64_t *)workspace;
+    uint64_t *partials = (uint64_t *)((char *)workspace + align_up((size_t)len * 8, 256));
+    if (ntiles == 0) {
+        hipLaunchKernelGGL(k_crit_empty, dim3(1), dim3(64), 0, s, counts);
+        return launch_status();
+    }
+    hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
+                       nbox, tc, ntiles);
+    exclusive_scan<uint64_t>(tc, len, partials, s);
+    hipLaunchKernelGGL(k_crit_fill, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
+                           nbox, tc, ntiles, w0, w1, lo[0], lo[1], lo[2], dims[0], dims[1], crit0,
+                           crit1, crit2, crit3, cap[0], cap[1], cap[2], cap[3]);
+    hipLaunchKernelGGL(k_crit_finish, dim3(1), dim3(64), 0, s, tc, ntiles, counts, cap[0], cap[1],
+                       cap[2], cap[3], dev_flags);
+    return launch_status();
+}

@@ -1,0 +1,97 @@
+// dms_d0_host.cpp -- host D0 pairing of the differentiable form (Section 2.6
+// and Algorithm 1, PairExtremaSaddles), run on the CPU after the GPU
+// gradient, the split the paper suggests for CPU+GPU nodes (Section 7).
+//
+// Extremum graph: from both vertices of every critical edge, follow the
+// vertex-edge vectors of the gradient down to a minimum (a vertex whose
+// record pairs it with nothing).  Triplets (edge, t0, t1) with t0 != t1 are
+// visited by increasing edge (Section 2.1 comparison: the edge's two vertex
+// orders, higher first); each joins the components of t0 and t1, and the
+// younger representative (higher order) dies at the edge.  Descents are
+// memoised per vertex.
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "dms.h"
+#include "dms_tables.hpp"
+
+namespace {
+
+struct Triplet {
+    int32_t k0, k1;  // orders of the higher and lower vertex of the edge
+    int64_t edge, t0, t1;
+};
+
+}  // namespace
+
+extern "C" int dms_d0_pairs_host(const uint32_t *rec, const int32_t *order, const int64_t dims[3],
+                                 const int64_t *crit1, int64_t n1, int64_t *pair_edge,
+                                 int64_t *pair_min, int64_t capacity, int64_t *npairs)
+{
+    if (!rec || !order || !dims || !npairs || n1 < 0 || capacity < 0) return DMS_E_ARG;
+    if (n1 > 0 && !crit1) return DMS_E_ARG;
+    if (capacity > 0 && (!pair_edge || !pair_min)) return DMS_E_ARG;
+    const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    if (nx < 1 || ny < 1 || nz < 1) return DMS_E_ARG;
+    const int64_t n = nx * ny * nz;
+    const dms::Tables &T = dms::kTables;
+    int64_t step[14];
+    for (int e = 0; e < 14; ++e) step[e] = T.nb[e][0] + nx * (T.nb[e][1] + ny * T.nb[e][2]);
+
+    // memoised descent: target[v] = minimum reached from v, -1 = not yet known
+    std::vector<int64_t> target(n, -1);
+    std::vector<int64_t> path;
+    auto descend = [&](int64_t v) -> int64_t {
+        path.clear();
+        while (target[v] < 0) {
+            const uint32_t *w = rec + 4 * v;
+            const uint64_t lo = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+            int delta = -1;
+            for (int e = 0; e < 14; ++e)
+                if (((lo >> (4 * e)) & 15u) == 1u) { delta = e; break; }
+            if (delta < 0) { target[v] = v; break; }
+            path.push_back(v);
+            v += step[delta];
+        }
+        const int64_t t = target[v];
+        for (int64_t u : path) target[u] = t;
+        return t;
+    };
+
+    std::vector<Triplet> trip;
+    trip.reserve((size_t)n1);
+    for (int64_t s = 0; s < n1; ++s) {
+        const int64_t a = crit1[s] >> 8;
+        const int e = (int)(crit1[s] & 255);
+        if (a < 0 || a >= n || e >= 14) return DMS_E_ARG;
+        const int64_t b = a + step[e];
+        if (b < 0 || b >= n) return DMS_E_ARG;
+        const int64_t t0 = descend(a), t1 = descend(b);
+        if (t0 != t1) trip.push_back({order[a], order[b], crit1[s], t0, t1});
+    }
+    std::sort(trip.begin(), trip.end(), [](const Triplet &x, const Triplet &y) {
+        return x.k0 != y.k0 ? x.k0 < y.k0 : x.k1 < y.k1;
+    });
+    std::vector<int64_t> rep(n);
+    for (int64_t v = 0; v < n; ++v) rep[v] = v;
+    auto find = [&](int64_t v) {
+        while (rep[v] != v) v = rep[v];
+        return v;
+    };
+    int64_t np = 0;
+    for (const Triplet &tr : trip) {
+        int64_t r0 = find(tr.t0), r1 = find(tr.t1);
+        if (r0 == r1) continue;
+        if (order[r0] < order[r1]) std::swap(r0, r1);
+        if (np < capacity) {
+            pair_edge[np] = tr.edge;
+            pair_min[np] = r0;
+        }
+        ++np;
+        rep[r0] = r1;
+        rep[tr.t0] = r1;
+    }
+    *npairs = np;
+    return np > capacity ? DMS_E_WORKSPACE : DMS_OK;
+}

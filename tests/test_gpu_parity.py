@@ -1,0 +1,251 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Integer outputs (orders, 128-bit records, critical codes) must be bit-exact;
+the FP64 backward must match the oracle gradient to 1e-10 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2505_21266_amd as dms
+from paper_2505_21266_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dms.lib()
+    yield
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _field(dims, kind, seed):
+    nx, ny, nz = dims
+    rng = np.random.default_rng(seed)
+    if kind == "noise":
+        return rng.random((nz, ny, nx), dtype=np.float32)
+    if kind == "ties":
+        return rng.integers(0, 5, (nz, ny, nx)).astype(np.float32)
+    if kind == "mixture":
+        return inputs.mixture_field((nz, ny, nx), 6, rng, 1e-3, np.float32)
+    if kind == "f64":
+        return inputs.mixture_field((nz, ny, nx), 6, rng, 1e-4, np.float64)
+    raise ValueError(kind)
+
+
+# ----------------------------------------------------------------- order
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 12289, 100003])
+@pytest.mark.parametrize("kind", ["noise", "ties"])
+def test_order_sizes(n, kind):
+    rng = np.random.default_rng(n)
+    v = rng.random(n, dtype=np.float32) if kind == "noise" else rng.integers(0, 7, n).astype(np.float32)
+    _say("order", n, kind)
+    got = dms.order(_dev(v)).cpu().numpy()
+    assert (got == oracle.order(v)).all()
+
+
+@pytest.mark.parametrize("n,kind", [(5000, "noise"), (70001, "ties"), (262144, "noise")])
+def test_order_f64(n, kind):
+    rng = np.random.default_rng(7 + n)
+    v = rng.random(n) if kind == "noise" else rng.integers(-3, 3, n).astype(np.float64)
+    _say("order f64", n, kind)
+    got = dms.order(_dev(v)).cpu().numpy()
+    assert (got == oracle.order(v)).all()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_order_special_values(dtype):
+    v = np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -0.0, 0.0, -1e-30, 1e-30, -np.inf, 5.0],
+                 dtype=dtype)
+    v = np.tile(v, 900)
+    got = dms.order(_dev(v)).cpu().numpy()
+    assert (got == oracle.order(v)).all()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_order_nan_flag(dtype):
+    v = np.random.default_rng(3).random(9000).astype(dtype)
+    v[4321] = np.nan
+    with pytest.raises(ValueError):
+        dms.order(_dev(v))
+
+
+def test_order_config1():
+    v = inputs.config1()
+    got = dms.order(_dev(v)).cpu().numpy()
+    assert (got == oracle.order(v)).all()
+
+
+# -------------------------------------------------------------- gradient
+
+GRAD_CASES = [
+    ((64, 64, 64), "noise", 1),
+    ((67, 5, 9), "noise", 2),
+    ((130, 3, 2), "ties", 3),
+    ((33, 17, 12), "mixture", 4),
+    ((70, 9, 6), "ties", 5),
+    ((1, 1, 1), "noise", 6),
+    ((9, 1, 1), "noise", 7),
+    ((1, 7, 1), "noise", 8),
+    ((1, 1, 6), "ties", 9),
+    ((5, 4, 1), "noise", 10),
+    ((1, 5, 6), "noise", 11),
+    ((65, 66, 3), "mixture", 12),
+]
+
+
+@pytest.mark.parametrize("dims,kind,seed", GRAD_CASES)
+def test_gradient_records(dims, kind, seed):
+    """Records from the oracle's order, and from the GPU order, both equal the
+    oracle's records bit for bit."""
+    v = _field(dims, kind, seed)
+    o = oracle.order(v)
+    want, counts, an = oracle.lower_stars(o, dims)
+    assert an == 0
+    _say("gradient", dims, kind)
+    got = dms.discrete_gradient(_dev(o)).cpu().numpy().view(np.uint32)
+    assert (got == want).all()
+    og = dms.order(_dev(v))
+    assert (og.cpu().numpy() == o).all()
+    got2 = dms.discrete_gradient(og).cpu().numpy().view(np.uint32)
+    assert (got2 == want).all()
+
+
+@pytest.mark.parametrize("dims,lo,hi", [((20, 18, 16), (1, 2, 1), (19, 17, 15)),
+                                        ((66, 10, 7), (1, 1, 1), (65, 9, 6)),
+                                        ((30, 30, 30), (0, 0, 0), (30, 1, 30)),
+                                        ((30, 30, 30), (5, 5, 5), (6, 6, 6))])
+def test_gradient_owned_box(dims, lo, hi):
+    v = _field(dims, "noise", 13)
+    o = oracle.order(v)
+    want, _, _ = oracle.lower_stars(o, dims, lo, hi)
+    _say("box", dims, lo, hi)
+    got = dms.discrete_gradient(_dev(o), lo, hi).cpu().numpy().view(np.uint32)
+    assert (got == want).all()
+
+
+def test_gradient_hand_worked_cube():
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cube2_hand.json")))
+    o = np.array(g["order"], np.int32).reshape(2, 2, 2)
+    want, _, _ = oracle.lower_stars(o, (2, 2, 2))
+    got = dms.discrete_gradient(_dev(o)).cpu().numpy().view(np.uint32)
+    assert (got == want).all()
+
+
+# -------------------------------------------------------------- critical
+
+@pytest.mark.parametrize("dims,kind,seed,box", [
+    ((64, 64, 64), "noise", 1, None),
+    ((40, 31, 22), "ties", 2, None),
+    ((45, 37, 29), "mixture", 3, None),
+    ((34, 34, 34), "noise", 4, ((1, 1, 1), (33, 33, 33))),
+    ((3, 3, 3), "noise", 5, None),
+    ((7, 1, 1), "noise", 6, None),
+])
+def test_critical_lists(dims, kind, seed, box):
+    v = _field(dims, kind, seed)
+    lo, hi = box if box else (None, None)
+    o = oracle.order(v)
+    rec, counts, _ = oracle.lower_stars(o, dims, lo, hi)
+    want, wcount = oracle.critical_simplices(rec, dims, lo, hi)
+    _say("critical", dims, kind, box)
+    _, grec, lists, gcounts = dms.gradient_pipeline(_dev(v), lo, hi)
+    assert (grec.cpu().numpy().view(np.uint32) == rec).all()
+    assert (gcounts.cpu().numpy() == wcount).all()
+    for d in range(4):
+        assert (lists[d].cpu().numpy() == want[d]).all(), d
+    if box is None:
+        c = wcount
+        assert c[0] - c[1] + c[2] - c[3] == 1
+
+
+def test_critical_capacity_flag():
+    dims = (40, 40, 40)
+    v = _field(dims, "noise", 21)
+    o = oracle.order(v)
+    rec, _, _ = oracle.lower_stars(o, dims)
+    want, wcount = oracle.critical_simplices(rec, dims)
+    cap = [max(int(c) // 2, 1) for c in wcount]
+    flags = dms.new_flags(torch.device("cuda"))
+    lists, counts = dms.critical_simplices(_dev(rec.view(np.int32)), dims, cap=cap, flags=flags)
+    f = int(flags.item())
+    assert f & dms.FLAG_CAPACITY
+    assert (counts.cpu().numpy() == wcount).all()
+    for d in range(4):
+        assert (lists[d].cpu().numpy() == want[d][: cap[d]]).all()
+
+
+def test_critical_empty_box():
+    dims = (8, 8, 8)
+    rec = torch.zeros((0, 4), dtype=torch.int32, device="cuda")
+    lists, counts = dms.critical_simplices(rec, dims, (2, 2, 2), (2, 5, 5))
+    assert counts.cpu().numpy().tolist() == [0, 0, 0, 0]
+
+
+def test_determinism_double_run():
+    dims = (50, 41, 33)
+    v = _dev(_field(dims, "ties", 31))
+    a = dms.gradient_pipeline(v)
+    b = dms.gradient_pipeline(v)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    for d in range(4):
+        assert torch.equal(a[2][d], b[2][d])
+
+
+# -------------------------------------------------------------- backward
+
+@pytest.mark.parametrize("shape", [(20, 22, 24), (32, 32, 32)])
+def test_backward_matches_oracle(shape):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(41)
+    f = inputs.min_gap_pass(inputs.mixture_field(shape, 6, rng, 1e-4, np.float64))
+    dims = (nx, ny, nz)
+    o = oracle.order(f)
+    rec, _, _ = oracle.lower_stars(o, dims)
+    crit, _ = oracle.critical_simplices(rec, dims)
+    pe, pm = oracle.d0_pairs(o, rec, dims, crit[1])
+    loss_o, grad_o, _ = oracle.d0_loss_grad(f, pe, pm, 0.05)
+    x = _dev(f).requires_grad_(True)
+    births, deaths = dms.PersistenceD0.apply(x)
+    assert (births.detach().cpu().numpy() == f.reshape(-1)[pm]).all()
+    assert (deaths.detach().cpu().numpy() == f.reshape(-1)[pe >> 8]).all()
+    from paper_2505_21266_amd.autograd import d0_loss
+    loss = d0_loss(births, deaths, 0.05)
+    loss.backward()
+    g = x.grad.cpu().numpy().reshape(-1)
+    assert abs(float(loss) - loss_o) <= 1e-12 * max(1.0, abs(loss_o))
+    scale = np.abs(grad_o).max()
+    assert np.all(np.abs(g - grad_o) <= 1e-10 * np.maximum(np.abs(grad_o), 1e-300) + 1e-300)
+    assert scale > 0
+
+
+def test_backward_kernel_runs():
+    # several deaths on one vertex, given adjacent: summed in pair order
+    bc = _dev(np.array([5 << 8, 9 << 8, 11 << 8], np.int64))
+    dc = _dev(np.array([(20 << 8) | 1, (20 << 8) | 4, (30 << 8) | 2], np.int64))
+    gb = _dev(np.array([1.0, 2.0, 3.0]))
+    gd = _dev(np.array([0.5, 0.25, -1.0]))
+    g = dms.gradient_backward(bc, dc, gb, gd, 40).cpu().numpy()
+    want = np.zeros(40)
+    want[[5, 9, 11]] = [1.0, 2.0, 3.0]
+    want[20] = 0.75
+    want[30] = -1.0
+    assert (g == want).all()

@@ -1,0 +1,118 @@
+"""Host-side checks of the HIP library (no GPU needed): it loads, exports
+every symbol include/dms.h declares, its compile-time star tables equal the
+oracle's, argument errors come back synchronously, and the host D0 pairing
+matches the oracle's Algorithm 1."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2505_21266_amd as dms
+from paper_2505_21266_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(dms.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return dms.lib()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dms.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dms_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 10
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert sorted(dms.SYMBOLS) == names
+
+
+def test_status_strings(L):
+    for s in range(6):
+        assert L.dms_status_str(s).decode().startswith("DMS_")
+    assert b"gfx950" in L.dms_version()
+
+
+def test_tables_match_oracle(L):
+    a = dms.star_tables()
+    b = oracle.star_tables()
+    for k in ("nb", "tri", "tet", "edge_tris", "tri_tets"):
+        assert (a[k] == b[k]).all(), k
+
+
+def _a3(v):
+    a = np.asarray(v, np.int64)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def test_argument_errors(L):
+    P = ctypes.c_void_p
+    fake = P(4096)  # never dereferenced: every call below fails its checks first
+    d, dp = _a3([4, 4, 4])
+    l, lp = _a3([0, 0, 0])
+    h, hp = _a3([4, 4, 4])
+    bad, badp = _a3([0, 0, 5])
+    # order
+    assert L.dms_order(None, 0, 10, fake, fake, 1 << 30, fake, None) == 1
+    assert L.dms_order(fake, 7, 10, fake, fake, 1 << 30, fake, None) == 1
+    assert L.dms_order(fake, 0, -1, fake, fake, 1 << 30, fake, None) == 1
+    assert L.dms_order(fake, 0, 1 << 31, fake, fake, 1 << 40, fake, None) == 2
+    assert L.dms_order(fake, 0, 1000, fake, fake, 10, fake, None) == 3
+    assert L.dms_order(fake, 0, 0, None, None, 0, None, None) == 0
+    assert L.dms_order_workspace_size(1000, 0) >= 16 * 1000
+    assert L.dms_order_workspace_size(1000, 1) >= 24 * 1000
+    # gradient
+    assert L.dms_discrete_gradient(None, dp, lp, hp, fake, None) == 1
+    assert L.dms_discrete_gradient(fake, dp, lp, badp, fake, None) == 1
+    big, bigp = _a3([2048, 2048, 1024])
+    assert L.dms_discrete_gradient(fake, bigp, lp, hp, fake, None) == 2
+    assert L.dms_discrete_gradient(fake, dp, lp, lp, fake, None) == 0  # empty box
+    neg, negp = _a3([-1, 0, 0])
+    assert L.dms_discrete_gradient(fake, dp, negp, hp, fake, None) == 1
+    # critical
+    cap, capp = _a3([0, 0, 0, 0])
+    assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, capp, fake, fake, 0,
+                                    fake, None) == 3
+    ncap, ncapp = _a3([0, -1, 0, 0])
+    assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, ncapp, fake, fake,
+                                    1 << 20, fake, None) == 1
+    c1, c1p = _a3([0, 5, 0, 0])
+    assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, c1p, fake, fake,
+                                    1 << 20, fake, None) == 1
+    assert L.dms_critical_workspace_size(dp, lp, badp) == 0
+    # backward
+    assert L.dms_gradient_backward(None, fake, fake, fake, 3, fake, 10, None) == 1
+    assert L.dms_gradient_backward(fake, fake, fake, fake, 3, None, 10, None) == 1
+    assert L.dms_gradient_backward(fake, fake, fake, fake, -1, fake, 10, None) == 1
+
+
+@pytest.mark.parametrize("dims,seed", [((8, 8, 8), 1), ((13, 9, 11), 2), ((32, 32, 32), 3)])
+def test_host_d0_matches_oracle(L, dims, seed):
+    nx, ny, nz = dims
+    rng = np.random.default_rng(seed)
+    v = inputs.mixture_field((nz, ny, nx), 8, rng, 1e-3, np.float64)
+    o = oracle.order(v).reshape(-1)
+    rec, _, _ = oracle.lower_stars(o, dims)
+    crit, _ = oracle.critical_simplices(rec, dims)
+    pe0, pm0 = oracle.d0_pairs(o, rec, dims, crit[1])
+    pe1, pm1 = dms.d0_pairs_host(rec, o, dims, crit[1])
+    assert (pe0 == pe1).all() and (pm0 == pm1).all()
+
+
+def test_host_d0_errors(L):
+    dims = (4, 4, 4)
+    o = np.arange(64, dtype=np.int32)
+    rec = np.zeros((64, 4), np.uint32)
+    with pytest.raises(dms.DmsError):
+        dms.d0_pairs_host(rec, o, dims, np.array([(100 << 8) | 3], np.int64))
