@@ -1,0 +1,174 @@
+"""Benchmark: discrete-gradient step of Discrete Morse Sandwich on one MI355X.
+
+One step = global vertex order (dms_order) + ProcessLowerStars gradient
+(dms_discrete_gradient) + critical-simplex extraction (dms_critical_simplices)
+over the workload below, with the input field already resident in HBM.
+
+Workload (default): a 1026^3 float32 block with a one-voxel ghost layer --
+512 isotropic Gaussians (seed 3) plus 1e-3 uniform noise -- whose owned
+1024^3 interior is processed: one GPU's share of a distributed run at its real
+shape.  Throughput = owned vertices per second.
+
+Printed: one JSON line with the metric, per-stage times (HIP events on the
+stream the kernels run on), the roofline object of the dominant kernel and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# algorithmic bytes per owned vertex of each stage (what the method must move)
+ALG_BYTES = {"order": 8.0, "gradient": 20.0, "critical": 16.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--owned", type=int, default=1024, help="owned vertices per side")
+    ap.add_argument("--bumps", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-planes", type=int, default=12, help="owned z-planes in the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(field, lo, hi, planes):
+    """Times the CPU oracle (order, ProcessLowerStars, extraction) on a slab of
+    the same field: `planes` owned z-planes plus their ghost planes."""
+    import oracle
+    k0 = lo[2]
+    sub = np.ascontiguousarray(field[k0 - 1:k0 + planes + 1])
+    nz, ny, nx = sub.shape
+    dims = (nx, ny, nz)
+    slo, shi = (lo[0], lo[1], 1), (hi[0], hi[1], 1 + planes)
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    o = oracle.order(sub)
+    t1 = time.perf_counter()
+    rec, counts, an = oracle.lower_stars(o, dims, slo, shi, nthreads=threads)
+    t2 = time.perf_counter()
+    oracle.critical_simplices(rec, dims, slo, shi)
+    t3 = time.perf_counter()
+    owned = (shi[0] - slo[0]) * (shi[1] - slo[1]) * (shi[2] - slo[2])
+    return {
+        "value": owned / (t3 - t0) / 1e9,
+        "unit": "Gvertices/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "%d owned z-planes (%dx%dx%d owned vertices, %.1f M) of the same field; "
+                  "order %.2f s (qsort, 1 thread), lower stars %.2f s (%d threads), "
+                  "extraction %.2f s (1 thread)" % (planes, shi[0] - slo[0], shi[1] - slo[1], planes,
+                                                   owned / 1e6, t1 - t0, t2 - t1, threads, t3 - t2),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2505_21266_amd as dms
+    from paper_2505_21266_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    field, lo, hi = inputs.config3(args.owned, args.bumps)
+    t_gen = time.perf_counter() - t_gen
+    nz, ny, nx = field.shape
+    dims = (nx, ny, nz)
+    owned = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
+    values = torch.from_numpy(field).to(dev)
+
+    stream = torch.cuda.current_stream(dev)
+    order_t = torch.empty(values.shape, dtype=torch.int32, device=dev)
+    rec = torch.empty((owned, 4), dtype=torch.int32, device=dev)
+    flags = dms.new_flags(dev)
+    # capacities from one exact run (the counts do not change between steps)
+    dms.order(values, out=order_t)
+    dms.discrete_gradient(order_t, lo, hi, out=rec)
+    lists, counts = dms.critical_simplices(rec, dims, lo, hi)
+    cap = counts.cpu().numpy().copy()
+    counts_t = torch.zeros(4, dtype=torch.int64, device=dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        dms.order(values, out=order_t, flags=flags, check=False)
+        if ev is not None:
+            ev[1].record(stream)
+        dms.discrete_gradient(order_t, lo, hi, out=rec)
+        if ev is not None:
+            ev[2].record(stream)
+        dms.critical_simplices(rec, dims, lo, hi, cap=cap, flags=flags, counts=counts_t)
+        if ev is not None:
+            ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if int(flags.item()) != 0:
+        raise RuntimeError("device flags set: %d" % int(flags.item()))
+    stage = {"order": [], "gradient": [], "critical": []}
+    for e in evs:
+        stage["order"].append(e[0].elapsed_time(e[1]))
+        stage["gradient"].append(e[1].elapsed_time(e[2]))
+        stage["critical"].append(e[2].elapsed_time(e[3]))
+    ms = {k: float(np.mean(v)) for k, v in stage.items()}
+    ms_step = wall / args.steps * 1e3
+    value = owned / (ms_step / 1e3) / 1e9
+
+    # dominant kernel: the single k_gradient launch of dms_discrete_gradient
+    dom = "gradient"
+    achieved = ALG_BYTES[dom] * owned / (ms[dom] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_gradient", "kernel_ms": round(ms[dom], 3)}
+    out = {
+        "metric": "discrete-gradient Gvertices/s (order + gradient + critical) at 1024^3 owned f32",
+        "value": round(value, 3),
+        "unit": "Gvertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "gauss1026_ghost: %dx%dx%d float32 block, owned %d^3 interior, "
+                               "%d Gaussians + 1e-3 U[0,1) noise (seed 3)"
+                               % (nx, ny, nz, args.owned, args.bumps),
+                   "owned_vertices": owned, "critical_counts": [int(c) for c in cap]},
+        "stage_ms": {k: round(v, 3) for k, v in ms.items()},
+        "stage_frac_hbm": {k: round(ALG_BYTES[k] * owned / (ms[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                           for k in ms},
+        "roofline": roofline,
+        "input_gen_s": round(t_gen, 1),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(field, lo, hi, min(args.cpu_planes, args.owned))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

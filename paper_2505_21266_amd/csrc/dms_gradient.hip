@@ -8,17 +8,14 @@
 //     the lower star L(x) (its vertex orders listed decreasingly, compared
 //     lexicographically) then equals the integer whose bits are the ranks of
 //     its lower vertices, so faces precede cofaces and "smallest" is an
-//     integer minimum;
-//  2. the cells of L(x) are enumerated in increasing key order (by highest
-//     rank, then second, then third), giving each its position p;
-//  3. Robins' two priority queues become bitsets over positions (pop-min is
-//     find-first-set), the unpaired ("free") cells bitsets over star-table
-//     indices, and the pairing runs in registers, with the two position maps
-//     in per-thread LDS;
-//  4. the outcome is packed into the 16-byte record described in dms.h.
-// Readings: "unpaired" = neither paired nor critical; only unpaired cells are
-// pushed onto the one-facet queue; the zero queue drops a cell as soon as it
-// is paired, which yields what lazy deletion yields.
+//     integer minimum, found by a bit-sliced scan over per-rank planes;
+//  2. Robins' pairing runs in registers on bitsets over the star's cells
+//     (unpaired cells, and a bit-sliced count of each cell's unpaired facets)
+//     -- see process_vertex for why the two priority queues need no storage;
+//  3. the outcome is packed into the 16-byte record described in dms.h.
+// Readings: "unpaired" = neither paired nor critical; only unpaired cells
+// enter the one-facet queue; entries of the zero queue that get paired are
+// dropped (Robins' lazy deletion gives the same pops).
 #include "dms_common.hpp"
 #include "dms_tables.hpp"
 
@@ -31,126 +28,71 @@ constexpr int HX = GX + 2, HY = GY + 2, HZ = GZ + 2;
 constexpr int kHalo = HX * HY * HZ;
 constexpr int32_t kAbsent = 0x7fffffff;
 
-// cell ids inside one star: edges 0..13, triangles 14..49, tets 50..73
-constexpr int kCellT = 14, kCellQ = 50, kCells = 74;
+// Star cells other than x and the edges: triangles t -> bit t, tets q -> bit
+// 36 + q of a 64-bit mask ("TQ space").
+constexpr uint64_t kTriBits = (1ull << 36) - 1;
 
 struct SharedTables {
-    uint8_t tri_id[14][14];
-    uint8_t tet_id[14][14][14];
-    uint8_t tri_ab[36];        // a | b << 4
-    uint8_t tri_slot[36];      // slot in edge_tris of a | slot of b << 4
-    uint8_t tri_tet0[36];      // first star tet of the triangle
-    uint16_t tri_edgemask[36];
-    uint32_t tri_tetmask[36];
-    uint64_t edge_trimask[14];
-    uint64_t tet_trimask[24];
+    uint64_t cont[14];     // TQ cells containing neighbour e
+    uint64_t facet[60];    // triangle: its two edges (neighbour bits); tet: its 3 triangles (TQ bits)
+    uint64_t cofacet[60];  // triangle: the tets containing it (TQ bits); tet: 0
+    uint8_t tri_ab[36];    // a | b << 4
+    uint8_t tri_slot[36];  // slot of t in the triangle list of a | of b << 4
+    uint8_t tri_tet0[36];  // first star tet containing t
+    uint8_t tet_abc[24][3];
+    uint8_t pad[4];
 };
 
-struct DeviceTables {
-    SharedTables t;
-};
-
-constexpr DeviceTables make_device_tables()
+constexpr SharedTables make_shared_tables()
 {
-    DeviceTables d{};
+    SharedTables d{};
     const Tables &T = kTables;
-    for (int a = 0; a < 14; ++a)
-        for (int b = 0; b < 14; ++b) {
-            d.t.tri_id[a][b] = (uint8_t)(T.tri_id[a][b] < 0 ? 255 : T.tri_id[a][b]);
-            for (int c = 0; c < 14; ++c)
-                d.t.tet_id[a][b][c] = (uint8_t)(T.tet_id[a][b][c] < 0 ? 255 : T.tet_id[a][b][c]);
-        }
+    for (int e = 0; e < 14; ++e) d.cont[e] = T.edge_trimask[e] | ((uint64_t)T.edge_tetmask[e] << 36);
     for (int t = 0; t < 36; ++t) {
-        d.t.tri_ab[t] = (uint8_t)(T.tri[t][0] | (T.tri[t][1] << 4));
-        d.t.tri_slot[t] = (uint8_t)(T.tri_slot[t][0] | (T.tri_slot[t][1] << 4));
-        d.t.tri_tet0[t] = (uint8_t)T.tri_tets[t][0];
-        d.t.tri_edgemask[t] = T.tri_edgemask[t];
-        d.t.tri_tetmask[t] = T.tri_tetmask[t];
+        d.facet[t] = T.tri_edgemask[t];
+        d.cofacet[t] = (uint64_t)T.tri_tetmask[t] << 36;
+        d.tri_ab[t] = (uint8_t)(T.tri[t][0] | (T.tri[t][1] << 4));
+        d.tri_slot[t] = (uint8_t)(T.tri_slot[t][0] | (T.tri_slot[t][1] << 4));
+        d.tri_tet0[t] = (uint8_t)T.tri_tets[t][0];
     }
-    for (int e = 0; e < 14; ++e) d.t.edge_trimask[e] = T.edge_trimask[e];
-    for (int q = 0; q < 24; ++q) d.t.tet_trimask[q] = T.tet_trimask[q];
+    for (int q = 0; q < 24; ++q) {
+        d.facet[36 + q] = T.tet_trimask[q];
+        d.cofacet[36 + q] = 0;
+        for (int c = 0; c < 3; ++c) d.tet_abc[q][c] = (uint8_t)T.tet[q][c];
+    }
     return d;
 }
 
-__constant__ DeviceTables g_tables = make_device_tables();
+__constant__ SharedTables g_tables = make_shared_tables();
+static_assert(sizeof(SharedTables) % 4 == 0, "copied as words");
 
-struct Bits128 {
-    uint64_t lo, hi;
-    __device__ __forceinline__ void set(int p)
+// Free-facet counts of the TQ cells, bit-sliced: count = 2*b1 + b0.
+struct Counts {
+    uint64_t b0, b1;
+    __device__ __forceinline__ void dec(uint64_t d)
     {
-        if (p < 64) lo |= 1ull << p; else hi |= 1ull << (p - 64);
-    }
-    __device__ __forceinline__ void clear(int p)
-    {
-        if (p < 64) lo &= ~(1ull << p); else hi &= ~(1ull << (p - 64));
-    }
-    __device__ __forceinline__ bool any() const { return (lo | hi) != 0; }
-    // index of the lowest set bit, which is cleared
-    __device__ __forceinline__ int pop_lowest()
-    {
-        if (lo) {
-            int p = __ffsll((unsigned long long)lo) - 1;
-            lo &= lo - 1;
-            return p;
-        }
-        int p = __ffsll((unsigned long long)hi) - 1;
-        hi &= hi - 1;
-        return p + 64;
+        b1 ^= d & ~b0;
+        b0 ^= d;
     }
 };
 
-// per-thread arrays, interleaved by thread so that equal indices of
-// neighbouring lanes sit in neighbouring bytes
-struct ThreadScratch {
-    uint8_t pos_of[kCells][kThreads];
-    uint8_t cell_at[kCells][kThreads];
-    uint8_t nb_at[14][kThreads];
-    uint16_t adj[14][kThreads];
-};
+__device__ __forceinline__ uint32_t nib(uint64_t packed, int i) { return (uint32_t)(packed >> (4 * i)) & 15u; }
 
-struct Star {
-    const SharedTables &T;
-    ThreadScratch &S;
-    int tid;
-    uint32_t fe;   // free edges (neighbour bits)
-    uint64_t ft;   // free triangles
-    uint32_t fq;   // free tets
-    Bits128 q1, q0;
-    uint64_t rec_lo, rec_hi;
-
-    __device__ __forceinline__ int pos(int cell) const { return S.pos_of[cell][tid]; }
-
-    __device__ __forceinline__ void set_tri_field(int t, uint32_t v)
-    {
-        const int b = 56 + 2 * t;
-        if (b < 64) rec_lo |= (uint64_t)v << b; else rec_hi |= (uint64_t)v << (b - 64);
-    }
-
-    // push free triangles of edge e with exactly one free edge
-    __device__ __forceinline__ void push_cofacets_edge(int e)
-    {
-        uint64_t m = T.edge_trimask[e] & ft;
-        while (m) {
-            const int t = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1;
-            if (__popc(T.tri_edgemask[t] & fe) == 1) q1.set(pos(kCellT + t));
-        }
-    }
-
-    // push free tets of triangle t with exactly one free triangle
-    __device__ __forceinline__ void push_cofacets_tri(int t)
-    {
-        uint32_t m = T.tri_tetmask[t] & fq;
-        while (m) {
-            const int q = __ffs(m) - 1;
-            m &= m - 1;
-            if (__popcll(T.tet_trimask[q] & ft) == 1) q1.set(pos(kCellQ + q));
-        }
-    }
-};
-
-__device__ void process_vertex(const int32_t *o, int32_t ox, const SharedTables &T,
-                               ThreadScratch &S, int tid, uint4 &out)
+// Robins' ProcessLowerStars for one vertex, from the orders of x and its 14
+// neighbours (kAbsent for neighbours outside the grid).
+//
+// The two priority queues of Robins' formulation are not stored: at any time
+// the one-facet queue, minus entries that have meanwhile lost their last
+// unpaired facet, is exactly the set of unpaired cells with one unpaired
+// facet (every cell enters it at the moment its count drops from two to
+// one), and when that set is empty the zero queue's live entries are exactly
+// the unpaired edges and the unpaired cells with no unpaired facet.  So each
+// step takes the smallest cell of the first set and pairs it with its
+// unpaired facet, or, if that set is empty, declares the smallest cell of the
+// second set critical.  "Smallest" is a bit-sliced minimum over key planes:
+// plane b holds the cells that contain the neighbour of rank b, and the key
+// of a cell is the integer with those bits (Section 2.1 comparison).
+__device__ void process_vertex(const int32_t *o, int32_t ox, const SharedTables &T, uint4 &out)
 {
     uint32_t low = 0;
 #pragma unroll
@@ -159,7 +101,7 @@ __device__ void process_vertex(const int32_t *o, int32_t ox, const SharedTables 
         out = make_uint4(0, 0, 0, 0);
         return;
     }
-    // 1. ranks among the lower neighbours (non-lower ones rank above them)
+    // ranks among the lower neighbours (non-lower ones rank above them)
     uint32_t ol[14], r[14];
 #pragma unroll
     for (int e = 0; e < 14; ++e) {
@@ -174,116 +116,102 @@ __device__ void process_vertex(const int32_t *o, int32_t ox, const SharedTables 
             r[a] += c;
             r[b] += 1u - c;
         }
-    uint32_t bitv[14];
-#pragma unroll
-    for (int e = 0; e < 14; ++e) bitv[e] = (low >> e) & 1u ? 1u << r[e] : 0u;
+    uint64_t nb_at = 0, rank_of = 0;  // rank -> neighbour, neighbour -> rank (4 bits each)
 #pragma unroll
     for (int e = 0; e < 14; ++e) {
-        if ((low >> e) & 1u) {
-            uint32_t a = 0;
-#pragma unroll
-            for (int f = 0; f < 14; ++f)
-                if ((kTables.link[e] >> f) & 1u) a |= bitv[f];
-            S.nb_at[r[e]][tid] = (uint8_t)e;
-            S.adj[r[e]][tid] = (uint16_t)a;
-        }
+        rank_of |= (uint64_t)r[e] << (4 * e);
+        if ((low >> e) & 1u) nb_at |= (uint64_t)e << (4 * r[e]);
     }
     const int m = __popc(low);
+    // complement of the key planes: nkp[b] = TQ cells NOT containing rank b
+    uint64_t nkp[14];
+#pragma unroll
+    for (int b = 0; b < 14; ++b) nkp[b] = b < m ? ~T.cont[nib(nb_at, b)] : ~0ull;
+    // TQ cells of L(x): no vertex outside the lower set
+    uint64_t out_tq = 0;
+#pragma unroll
+    for (int e = 0; e < 14; ++e)
+        if (!((low >> e) & 1u)) out_tq |= kTables.edge_trimask[e] | ((uint64_t)kTables.edge_tetmask[e] << 36);
+    const uint64_t in_l = ~out_tq & ((1ull << 60) - 1);
 
-    // 2. enumerate L(x) \ {x} in key order
-    Star st{T, S, tid, 0, 0, 0, {0, 0}, {0, 0}, 0, 0};
-    uint64_t in_t = 0;
-    uint32_t in_q = 0;
-    int P = 0;
-    for (int h = 0; h < m; ++h) {
-        const int e = S.nb_at[h][tid];
-        const uint32_t ah = S.adj[h][tid];
-        S.pos_of[e][tid] = (uint8_t)P;
-        S.cell_at[P][tid] = (uint8_t)e;
-        if (h > 0) st.q0.set(P);
-        ++P;
-        uint32_t A = ah & ((1u << h) - 1u);
-        while (A) {
-            const int s = __ffs(A) - 1;
-            A &= A - 1;
-            const int f = S.nb_at[s][tid];
-            const int t = T.tri_id[e][f];
-            in_t |= 1ull << t;
-            S.pos_of[kCellT + t][tid] = (uint8_t)P;
-            S.cell_at[P][tid] = (uint8_t)(kCellT + t);
-            ++P;
-            uint32_t B = ah & S.adj[s][tid] & ((1u << s) - 1u);
-            while (B) {
-                const int u = __ffs(B) - 1;
-                B &= B - 1;
-                const int g = S.nb_at[u][tid];
-                const int q = T.tet_id[e][f][g];
-                in_q |= 1u << q;
-                S.pos_of[kCellQ + q][tid] = (uint8_t)P;
-                S.cell_at[P][tid] = (uint8_t)(kCellQ + q);
-                ++P;
-            }
-        }
+    uint64_t ftq = in_l;                    // unpaired TQ cells
+    uint32_t fe = low;                      // unpaired edges, by neighbour
+    uint32_t fr = (1u << m) - 1u;               // unpaired edges, by rank
+    Counts cnt{(1ull << 60) - 1 - kTriBits, (1ull << 60) - 1};  // triangles 2, tets 3
+    uint64_t rec_lo = 0, rec_hi = 0;
+
+    // pair x with its smallest edge (the lowest lower neighbour)
+    {
+        const int d = nib(nb_at, 0);
+        fe &= ~(1u << d);
+        fr &= ~1u;
+        rec_lo |= 1ull << (4 * d);
+        cnt.dec(T.cont[d] & kTriBits);
     }
-
-    // 3. Robins' pairing
-    const int delta = S.nb_at[0][tid];  // smallest edge: lowest lower neighbour, position 0
-    st.fe = low & ~(1u << delta);
-    st.ft = in_t;
-    st.fq = in_q;
-    st.rec_lo = 1ull << (4 * delta);  // delta is paired with x
-    st.push_cofacets_edge(delta);
-    for (;;) {
-        while (st.q1.any()) {
-            const int p = st.q1.pop_lowest();
-            const int c = S.cell_at[p][tid];
-            if (c < kCellQ) {  // triangle
-                const int t = c - kCellT;
-                const uint32_t fm = T.tri_edgemask[t] & st.fe;
-                if (fm == 0) {
-                    st.q0.set(p);
+    for (int step = 0; step < 80; ++step) {
+        const uint64_t one = ftq & cnt.b0 & ~cnt.b1;
+        const bool pair_mode = one != 0;
+        uint64_t S = pair_mode ? one : (ftq & ~cnt.b0 & ~cnt.b1);
+        if (!pair_mode && S == 0 && fr == 0) break;
+#pragma unroll
+        for (int b = 13; b >= 0; --b) {
+            const uint64_t z = S & nkp[b];
+            S = z ? z : S;
+        }
+        const int a = S ? __ffsll((unsigned long long)S) - 1 : -1;  // smallest TQ cell
+        bool edge_wins = false;
+        int re = 0;
+        if (!pair_mode) {
+            if (fr) {
+                re = __ffs(fr) - 1;
+                if (a < 0) {
+                    edge_wins = true;
                 } else {
-                    const int b = __ffs(fm) - 1;  // its only free edge
-                    st.fe &= ~(1u << b);
-                    st.ft &= ~(1ull << t);
-                    const uint32_t ab = T.tri_ab[t], sl = T.tri_slot[t];
-                    const uint32_t slot = (int)(ab & 15u) == b ? (sl & 15u) : (sl >> 4);
-                    st.rec_lo |= (uint64_t)(3u + slot) << (4 * b);
-                    st.q0.clear(st.pos(b));
-                    st.push_cofacets_tri(t);
-                    st.push_cofacets_edge(b);
-                }
-            } else {  // tet
-                const int q = c - kCellQ;
-                const uint64_t fm = T.tet_trimask[q] & st.ft;
-                if (fm == 0) {
-                    st.q0.set(p);
-                } else {
-                    const int b = __ffsll((unsigned long long)fm) - 1;  // its only free triangle
-                    st.ft &= ~(1ull << b);
-                    st.fq &= ~(1u << q);
-                    st.set_tri_field(b, T.tri_tet0[b] == q ? 1u : 2u);
-                    st.q0.clear(st.pos(kCellT + b));
-                    st.push_cofacets_tri(b);
+                    // the edge of rank re is smaller iff re <= the top rank of cell a
+                    int top;
+                    if (a < 36) {
+                        const uint32_t ab = T.tri_ab[a];
+                        top = max(nib(rank_of, ab & 15u), nib(rank_of, ab >> 4));
+                    } else {
+                        const int q = a - 36;
+                        top = max(max(nib(rank_of, T.tet_abc[q][0]), nib(rank_of, T.tet_abc[q][1])),
+                                  nib(rank_of, T.tet_abc[q][2]));
+                    }
+                    edge_wins = re <= top;
                 }
             }
         }
-        if (!st.q0.any()) break;
-        const int p = st.q0.pop_lowest();
-        const int c = S.cell_at[p][tid];
-        if (c < kCellT) {  // critical edge
-            st.fe &= ~(1u << c);
-            st.rec_lo |= 2ull << (4 * c);
-            st.push_cofacets_edge(c);
-        } else if (c < kCellQ) {  // critical triangle
-            st.ft &= ~(1ull << (c - kCellT));
-            st.push_cofacets_tri(c - kCellT);
-        } else {  // critical tet
-            st.fq &= ~(1u << (c - kCellQ));
+        if (edge_wins) {  // critical edge
+            const int e = nib(nb_at, re);
+            fe &= ~(1u << e);
+            fr &= ~(1u << re);
+            rec_lo |= 2ull << (4 * e);
+            cnt.dec(T.cont[e] & kTriBits);
+        } else if (!pair_mode) {  // critical triangle or tet
+            ftq &= ~(1ull << a);
+            cnt.dec(T.cofacet[a]);
+        } else if (a < 36) {  // triangle a takes its only unpaired edge
+            const int e = __ffs((uint32_t)T.facet[a] & fe) - 1;
+            fe &= ~(1u << e);
+            fr &= ~(1u << nib(rank_of, e));
+            const uint32_t ab = T.tri_ab[a], sl = T.tri_slot[a];
+            const uint32_t slot = (int)(ab & 15u) == e ? (sl & 15u) : (sl >> 4);
+            rec_lo |= (uint64_t)(3u + slot) << (4 * e);
+            cnt.dec(T.cont[e] & kTriBits);
+            ftq &= ~(1ull << a);
+            cnt.dec(T.cofacet[a]);
+        } else {  // tet takes its only unpaired triangle
+            const int q = a - 36;
+            const int t = __ffsll((unsigned long long)(T.facet[a] & ftq)) - 1;
+            ftq &= ~((1ull << t) | (1ull << a));
+            cnt.dec(T.cofacet[t]);
+            const uint64_t v = T.tri_tet0[t] == q ? 1u : 2u;
+            const int bit = 56 + 2 * t;
+            if (bit < 64) rec_lo |= v << bit; else rec_hi |= v << (bit - 64);
         }
     }
-    out = make_uint4((uint32_t)st.rec_lo, (uint32_t)(st.rec_lo >> 32), (uint32_t)st.rec_hi,
-                     (uint32_t)(st.rec_hi >> 32));
+    out = make_uint4((uint32_t)rec_lo, (uint32_t)(rec_lo >> 32), (uint32_t)rec_hi,
+                     (uint32_t)(rec_hi >> 32));
 }
 
 __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict__ order,
@@ -295,11 +223,10 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict
 {
     __shared__ SharedTables T;
     __shared__ int32_t tile[kHalo];
-    __shared__ ThreadScratch S;
 
     const int tid = threadIdx.x;
     {
-        const uint32_t *src = (const uint32_t *)&g_tables.t;
+        const uint32_t *src = (const uint32_t *)&g_tables;
         uint32_t *dst = (uint32_t *)&T;
         for (int i = tid; i < (int)(sizeof(SharedTables) / 4); i += kThreads) dst[i] = src[i];
     }
@@ -324,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict
     for (int e = 0; e < 14; ++e)
         o[e] = tile[c + kTables.nb[e][0] + HX * (kTables.nb[e][1] + HY * kTables.nb[e][2])];
     uint4 r;
-    process_vertex(o, tile[c], T, S, tid, r);
+    process_vertex(o, tile[c], T, r);
     rec[ox_ + w0 * (oy_ + w1 * oz_)] = r;
 }
 
