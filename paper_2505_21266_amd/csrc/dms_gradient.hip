@@ -27,6 +27,7 @@ constexpr int kThreads = GX * GY * GZ;
 constexpr int HX = GX + 2, HY = GY + 2, HZ = GZ + 2;
 constexpr int kHalo = HX * HY * HZ;
 constexpr int32_t kAbsent = 0x7fffffff;
+constexpr int kSizeBins = 76;  // lower-star sizes 0..75
 
 // Star cells other than x and the edges: triangles t -> bit t, tets q -> bit
 // 36 + q of a 64-bit mask ("TQ space").
@@ -78,8 +79,28 @@ struct Counts {
 
 __device__ __forceinline__ uint32_t nib(uint64_t packed, int i) { return (uint32_t)(packed >> (4 * i)) & 15u; }
 
+// Lower-neighbour mask of x: bit e set if neighbour e precedes x.
+__device__ __forceinline__ uint32_t lower_mask(const int32_t *o, int32_t ox)
+{
+    uint32_t low = 0;
+#pragma unroll
+    for (int e = 0; e < 14; ++e) low |= (o[e] < ox ? 1u : 0u) << e;
+    return low;
+}
+
+// TQ cells of L(x): those with no vertex outside the lower set.
+__device__ __forceinline__ uint64_t lower_star_tq(uint32_t low)
+{
+    uint64_t out_tq = 0;
+#pragma unroll
+    for (int e = 0; e < 14; ++e)
+        if (!((low >> e) & 1u)) out_tq |= kTables.edge_trimask[e] | ((uint64_t)kTables.edge_tetmask[e] << 36);
+    return ~out_tq & ((1ull << 60) - 1);
+}
+
 // Robins' ProcessLowerStars for one vertex, from the orders of x and its 14
-// neighbours (kAbsent for neighbours outside the grid).
+// neighbours (kAbsent for neighbours outside the grid).  mmax is an upper
+// bound, uniform over the wave, of the number of lower neighbours.
 //
 // The two priority queues of Robins' formulation are not stored: at any time
 // the one-facet queue, minus entries that have meanwhile lost their last
@@ -92,11 +113,10 @@ __device__ __forceinline__ uint32_t nib(uint64_t packed, int i) { return (uint32
 // second set critical.  "Smallest" is a bit-sliced minimum over key planes:
 // plane b holds the cells that contain the neighbour of rank b, and the key
 // of a cell is the integer with those bits (Section 2.1 comparison).
-__device__ void process_vertex(const int32_t *o, int32_t ox, const SharedTables &T, uint4 &out)
+__device__ void process_vertex(const int32_t *o, int32_t ox, int mmax, const SharedTables &T,
+                               uint4 &out)
 {
-    uint32_t low = 0;
-#pragma unroll
-    for (int e = 0; e < 14; ++e) low |= (o[e] < ox ? 1u : 0u) << e;
+    const uint32_t low = lower_mask(o, ox);
     if (low == 0) {  // L(x) = {x}: x is critical
         out = make_uint4(0, 0, 0, 0);
         return;
@@ -127,16 +147,10 @@ __device__ void process_vertex(const int32_t *o, int32_t ox, const SharedTables 
     uint64_t nkp[14];
 #pragma unroll
     for (int b = 0; b < 14; ++b) nkp[b] = b < m ? ~T.cont[nib(nb_at, b)] : ~0ull;
-    // TQ cells of L(x): no vertex outside the lower set
-    uint64_t out_tq = 0;
-#pragma unroll
-    for (int e = 0; e < 14; ++e)
-        if (!((low >> e) & 1u)) out_tq |= kTables.edge_trimask[e] | ((uint64_t)kTables.edge_tetmask[e] << 36);
-    const uint64_t in_l = ~out_tq & ((1ull << 60) - 1);
 
-    uint64_t ftq = in_l;                    // unpaired TQ cells
-    uint32_t fe = low;                      // unpaired edges, by neighbour
-    uint32_t fr = (1u << m) - 1u;               // unpaired edges, by rank
+    uint64_t ftq = lower_star_tq(low);  // unpaired TQ cells
+    uint32_t fe = low;                  // unpaired edges, by neighbour
+    uint32_t fr = (1u << m) - 1u;       // unpaired edges, by rank
     Counts cnt{(1ull << 60) - 1 - kTriBits, (1ull << 60) - 1};  // triangles 2, tets 3
     uint64_t rec_lo = 0, rec_hi = 0;
 
@@ -155,65 +169,78 @@ __device__ void process_vertex(const int32_t *o, int32_t ox, const SharedTables 
         if (!pair_mode && S == 0 && fr == 0) break;
 #pragma unroll
         for (int b = 13; b >= 0; --b) {
-            const uint64_t z = S & nkp[b];
-            S = z ? z : S;
-        }
-        const int a = S ? __ffsll((unsigned long long)S) - 1 : -1;  // smallest TQ cell
-        bool edge_wins = false;
-        int re = 0;
-        if (!pair_mode) {
-            if (fr) {
-                re = __ffs(fr) - 1;
-                if (a < 0) {
-                    edge_wins = true;
-                } else {
-                    // the edge of rank re is smaller iff re <= the top rank of cell a
-                    int top;
-                    if (a < 36) {
-                        const uint32_t ab = T.tri_ab[a];
-                        top = max(nib(rank_of, ab & 15u), nib(rank_of, ab >> 4));
-                    } else {
-                        const int q = a - 36;
-                        top = max(max(nib(rank_of, T.tet_abc[q][0]), nib(rank_of, T.tet_abc[q][1])),
-                                  nib(rank_of, T.tet_abc[q][2]));
-                    }
-                    edge_wins = re <= top;
-                }
+            if (b < mmax) {
+                const uint64_t z = S & nkp[b];
+                S = z ? z : S;
             }
         }
-        if (edge_wins) {  // critical edge
-            const int e = nib(nb_at, re);
-            fe &= ~(1u << e);
-            fr &= ~(1u << re);
-            rec_lo |= 2ull << (4 * e);
-            cnt.dec(T.cont[e] & kTriBits);
-        } else if (!pair_mode) {  // critical triangle or tet
-            ftq &= ~(1ull << a);
-            cnt.dec(T.cofacet[a]);
-        } else if (a < 36) {  // triangle a takes its only unpaired edge
-            const int e = __ffs((uint32_t)T.facet[a] & fe) - 1;
+        const bool have_a = S != 0;
+        const int a = have_a ? __ffsll((unsigned long long)S) - 1 : 0;  // smallest TQ cell
+        const bool is_tri = a < 36;
+        // top rank of cell a (for comparing with the smallest edge)
+        int top;
+        if (is_tri) {
+            const uint32_t ab = T.tri_ab[a];
+            top = max(nib(rank_of, ab & 15u), nib(rank_of, ab >> 4));
+        } else {
+            const int q = a - 36;
+            top = max(max(nib(rank_of, T.tet_abc[q][0]), nib(rank_of, T.tet_abc[q][1])),
+                      nib(rank_of, T.tet_abc[q][2]));
+        }
+        const int re = fr ? __ffs(fr) - 1 : 31;
+        // an unpaired edge is smaller than cell a iff its rank is <= a's top rank
+        const bool edge_wins = !pair_mode && fr != 0 && (!have_a || re <= top);
+        const uint64_t fa = T.facet[a];
+        const uint64_t cof_a = T.cofacet[a];
+
+        uint64_t D = 0;  // cells losing an unpaired facet in this step
+        // the edge that stops being unpaired, if any: a critical edge, or the
+        // only unpaired edge of a triangle being paired
+        int e = -1;
+        uint32_t ev = 0;
+        if (edge_wins) {
+            e = nib(nb_at, re);
+            ev = 2;
+        } else if (pair_mode && is_tri) {
+            e = __ffs((uint32_t)fa & fe) - 1;
+            const uint32_t ab = T.tri_ab[a], sl = T.tri_slot[a];
+            ev = 3u + ((int)(ab & 15u) == e ? (sl & 15u) : (sl >> 4));
+        }
+        if (e >= 0) {
             fe &= ~(1u << e);
             fr &= ~(1u << nib(rank_of, e));
-            const uint32_t ab = T.tri_ab[a], sl = T.tri_slot[a];
-            const uint32_t slot = (int)(ab & 15u) == e ? (sl & 15u) : (sl >> 4);
-            rec_lo |= (uint64_t)(3u + slot) << (4 * e);
-            cnt.dec(T.cont[e] & kTriBits);
+            rec_lo |= (uint64_t)ev << (4 * e);
+            D |= T.cont[e] & kTriBits;
+        }
+        if (!edge_wins) {  // cell a stops being unpaired (critical or paired as head)
             ftq &= ~(1ull << a);
-            cnt.dec(T.cofacet[a]);
-        } else {  // tet takes its only unpaired triangle
-            const int q = a - 36;
-            const int t = __ffsll((unsigned long long)(T.facet[a] & ftq)) - 1;
-            ftq &= ~((1ull << t) | (1ull << a));
-            cnt.dec(T.cofacet[t]);
-            const uint64_t v = T.tri_tet0[t] == q ? 1u : 2u;
+            D |= cof_a;
+        }
+        if (pair_mode && !is_tri) {  // a tet takes its only unpaired triangle t
+            const int t = __ffsll((unsigned long long)(fa & ftq)) - 1;
+            ftq &= ~(1ull << t);
+            D |= T.cofacet[t];
+            const uint64_t v = T.tri_tet0[t] == a - 36 ? 1u : 2u;
             const int bit = 56 + 2 * t;
             if (bit < 64) rec_lo |= v << bit; else rec_hi |= v << (bit - 64);
         }
+        cnt.dec(D);
     }
     out = make_uint4((uint32_t)rec_lo, (uint32_t)(rec_lo >> 32), (uint32_t)rec_hi,
                      (uint32_t)(rec_hi >> 32));
 }
 
+__device__ __forceinline__ void gather_orders(const int32_t *tile, int c, int32_t *o)
+{
+#pragma unroll
+    for (int e = 0; e < 14; ++e)
+        o[e] = tile[c + kTables.nb[e][0] + HX * (kTables.nb[e][1] + HY * kTables.nb[e][2])];
+}
+
+// Each block stages the orders of a GX x GY x GZ tile of the owned box plus
+// a one-vertex halo, then assigns its vertices to threads sorted by the size
+// of their lower stars, so that the vertices of a wave need similar numbers
+// of steps (a wave runs as long as its slowest lane).
 __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict__ order,
                                                        int64_t nx, int64_t ny, int64_t nz,
                                                        int64_t lo0, int64_t lo1, int64_t lo2,
@@ -223,6 +250,8 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict
 {
     __shared__ SharedTables T;
     __shared__ int32_t tile[kHalo];
+    __shared__ uint32_t bins[kSizeBins];
+    __shared__ uint16_t perm[kThreads];
 
     const int tid = threadIdx.x;
     {
@@ -230,6 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict
         uint32_t *dst = (uint32_t *)&T;
         for (int i = tid; i < (int)(sizeof(SharedTables) / 4); i += kThreads) dst[i] = src[i];
     }
+    for (int i = tid; i < kSizeBins; i += kThreads) bins[i] = 0;
     const int64_t b = blockIdx.x;
     const int64_t bx = b % bx_count, by = (b / bx_count) % by_count, bz = b / (bx_count * by_count);
     const int64_t x0 = lo0 + bx * GX - 1, y0 = lo1 + by * GY - 1, z0 = lo2 + bz * GZ - 1;
@@ -242,16 +272,52 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict
     }
     __syncthreads();
 
-    const int tx = tid % GX, ty = (tid / GX) % GY, tz = tid / (GX * GY);
+    // lower-star size of the vertex at tile slot tid (0 outside the box)
+    int size = 0;
+    {
+        const int tx = tid % GX, ty = (tid / GX) % GY, tz = tid / (GX * GY);
+        if (bx * GX + tx < w0 && by * GY + ty < w1 && bz * GZ + tz < w2) {
+            const int c = (tx + 1) + HX * ((ty + 1) + HY * (tz + 1));
+            int32_t o[14];
+            gather_orders(tile, c, o);
+            const uint32_t low = lower_mask(o, tile[c]);
+            size = 1 + __popc(low) + __popcll(lower_star_tq(low));
+        }
+    }
+    const uint32_t slot = atomicAdd(&bins[size], 1u);
+    __syncthreads();
+    if (tid < kWave) {  // exclusive scan of the bins by the first wave
+        uint32_t v0 = tid < kSizeBins ? bins[tid] : 0u;
+        uint32_t v1 = tid + kWave < kSizeBins ? bins[tid + kWave] : 0u;
+        uint32_t i0 = v0, i1 = v1;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t t0 = __shfl_up(i0, off), t1 = __shfl_up(i1, off);
+            if (tid >= off) { i0 += t0; i1 += t1; }
+        }
+        const uint32_t tot0 = __shfl(i0, kWave - 1);
+        if (tid < kSizeBins) bins[tid] = i0 - v0;
+        if (tid + kWave < kSizeBins) bins[tid + kWave] = tot0 + i1 - v1;
+    }
+    __syncthreads();
+    perm[bins[size] + slot] = (uint16_t)tid;
+    __syncthreads();
+
+    const int v = perm[tid];
+    const int tx = v % GX, ty = (v / GX) % GY, tz = v / (GX * GY);
     const int64_t ox_ = bx * GX + tx, oy_ = by * GY + ty, oz_ = bz * GZ + tz;  // box coordinates
-    if (ox_ >= w0 || oy_ >= w1 || oz_ >= w2) return;
+    const bool inside = ox_ < w0 && oy_ < w1 && oz_ < w2;
     const int c = (tx + 1) + HX * ((ty + 1) + HY * (tz + 1));
     int32_t o[14];
+    gather_orders(tile, c, o);
+    const int m = inside ? __popc(lower_mask(o, tile[c])) : 0;
+    int mmax = m;
 #pragma unroll
-    for (int e = 0; e < 14; ++e)
-        o[e] = tile[c + kTables.nb[e][0] + HX * (kTables.nb[e][1] + HY * kTables.nb[e][2])];
+    for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
+    mmax = __builtin_amdgcn_readfirstlane(mmax);
+    if (!inside) return;
     uint4 r;
-    process_vertex(o, tile[c], T, r);
+    process_vertex(o, tile[c], mmax, T, r);
     rec[ox_ + w0 * (oy_ + w1 * oz_)] = r;
 }
 
