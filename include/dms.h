@@ -168,6 +168,46 @@ int dms_d0_pairs_host(const uint32_t *rec, const int32_t *order, const int64_t d
                       const int64_t *crit1, int64_t n1, int64_t *pair_edge, int64_t *pair_min,
                       int64_t capacity, int64_t *npairs);
 
+/* ----------------------------------------------------------------------------
+ * Batched form: many float32 fields of uneven shapes (ensemble members, time
+ * steps) through order, gradient and extraction in one graph launch.  Each
+ * field is processed exactly as the single-field calls would process it
+ * with box = the whole field (Sections 2.1, 2.3, 2.6); the batch only shares
+ * launches.
+ *
+ * dms_batch_create: dims = [host] 3 * nfields sides (x, y, z) of the fields,
+ * in order; dtype must be DMS_F32.  tune != 0 times the gradient tile
+ * shapes on the first run (that run synchronises) unless tune_cache (a file
+ * path, may be NULL) already holds a choice for these shapes; the choice is
+ * appended to tune_cache.  Allocates small device tables and a private
+ * capture stream; returns DMS_E_ARG, DMS_E_SIZE (over 1024 fields or more
+ * than 2^31 - 1 vertices in all), DMS_E_UNSUPPORTED (dtype), DMS_E_HIP.
+ *
+ * dms_batch_run: values = all fields concatenated in order (field f starts at
+ * off[f] = sum of the vertex counts of the fields before it), device float32;
+ * order (int32) and rec (4 uint32 per vertex) are concatenated the same way
+ * and hold each field's own order and records.  crit0..crit3 receive, per
+ * dimension, the critical cells of all fields, field after field, as
+ * (field-local vertex id << 8) | local index; cap[4] [host] are their
+ * capacities.  counts (device, 4 * nfields int64) receives counts[4 f + d];
+ * offsets (device, 4 * (nfields + 1) int64) receives the first slot of field
+ * f in list d at offsets[d * (nfields + 1) + f], and the total at f = nfields.
+ * The first run (and any run whose pointers or capacities differ from the
+ * previous one) records the launches into a hipGraph; the others replay it
+ * on `stream`.  dev_flags as for the single-field calls.
+ * ------------------------------------------------------------------------- */
+typedef struct dms_batch dms_batch;
+int dms_batch_create(const int64_t *dims, int nfields, int dtype, int tune, const char *tune_cache,
+                     dms_batch **out);
+size_t dms_batch_workspace_size(const dms_batch *batch);
+int64_t dms_batch_total(const dms_batch *batch);   /* vertices in all fields */
+int dms_batch_variant(const dms_batch *batch);     /* chosen gradient tile shape: 0 64x4, 1 32x8, 2 16x16 */
+int dms_batch_run(dms_batch *batch, const void *values, int32_t *order, uint32_t *rec, int64_t *crit0,
+                  int64_t *crit1, int64_t *crit2, int64_t *crit3, const int64_t cap[4],
+                  int64_t *counts, int64_t *offsets, void *workspace, size_t workspace_bytes,
+                  uint32_t *dev_flags, void *stream);
+void dms_batch_destroy(dms_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,9 @@ STATUS = {0: "DMS_OK", 1: "DMS_E_ARG", 2: "DMS_E_SIZE", 3: "DMS_E_WORKSPACE",
 # every symbol include/dms.h declares
 SYMBOLS = ("dms_status_str", "dms_version", "dms_star_tables", "dms_order_workspace_size",
            "dms_order", "dms_discrete_gradient", "dms_critical_workspace_size",
-           "dms_critical_simplices", "dms_gradient_backward", "dms_d0_pairs_host")
+           "dms_critical_simplices", "dms_gradient_backward", "dms_d0_pairs_host",
+           "dms_batch_create", "dms_batch_workspace_size", "dms_batch_total", "dms_batch_variant",
+           "dms_batch_run", "dms_batch_destroy")
 
 _lib = None
 
@@ -59,8 +61,18 @@ def lib():
     L.dms_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
     L.dms_gradient_backward.argtypes = [P, P, P, P, I64, P, I64, P]
     L.dms_d0_pairs_host.argtypes = [P, P, P, P, I64, P, P, I64, P]
+    L.dms_batch_create.argtypes = [P, I, I, I, ctypes.c_char_p, P]
+    L.dms_batch_workspace_size.argtypes = [P]
+    L.dms_batch_workspace_size.restype = SZ
+    L.dms_batch_total.argtypes = [P]
+    L.dms_batch_total.restype = I64
+    L.dms_batch_variant.argtypes = [P]
+    L.dms_batch_run.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
+    L.dms_batch_destroy.argtypes = [P]
+    L.dms_batch_destroy.restype = None
     for f in ("dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_critical_simplices",
-              "dms_gradient_backward", "dms_d0_pairs_host"):
+              "dms_gradient_backward", "dms_d0_pairs_host", "dms_batch_create", "dms_batch_variant",
+              "dms_batch_run"):
         getattr(L, f).restype = I
     _lib = L
     return L
@@ -284,6 +296,86 @@ def gradient_pipeline(values, lo=None, hi=None, cap=None):
     rec = discrete_gradient(o, lo, hi)
     lists, counts = critical_simplices(rec, dims, lo, hi, cap=cap)
     return o, rec, lists, counts
+
+
+class Batch:
+    """Batched form (dms_batch_*): many float32 fields of uneven sides.
+
+    sides: sequence of (nx, ny, nz).  run(values) takes the fields
+    concatenated in one GPU float32 tensor and returns the concatenated
+    orders and records, the four critical lists (field after field, codes
+    with field-local vertex ids), per-field counts [nfields, 4] and list
+    offsets [4, nfields + 1].  Keep the output buffers (reuse=True) and the
+    launches replay one captured hipGraph.
+    """
+
+    def __init__(self, sides, tune=False, cache=None, device=None):
+        import torch
+        L = lib()
+        self.sides = np.ascontiguousarray(np.asarray(sides, dtype=np.int64).reshape(-1, 3))
+        self.nfields = self.sides.shape[0]
+        self.ptr = ctypes.c_void_p()
+        c = cache.encode() if cache else None
+        _check(L.dms_batch_create(self.sides.ctypes.data_as(ctypes.c_void_p), self.nfields, DMS_F32,
+                                  int(bool(tune)), c, ctypes.byref(self.ptr)), "dms_batch_create")
+        sizes = self.sides.prod(axis=1)
+        self.off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        self.total = int(L.dms_batch_total(self.ptr))
+        self.device = device or torch.device("cuda")
+        self.ws = torch.empty(max(int(L.dms_batch_workspace_size(self.ptr)), 256), dtype=torch.uint8,
+                              device=self.device)
+        self.bufs = None
+
+    @property
+    def variant(self):
+        return int(lib().dms_batch_variant(self.ptr))
+
+    def _alloc(self, cap):
+        import torch
+        dev = self.device
+        return dict(order=torch.empty(self.total, dtype=torch.int32, device=dev),
+                    rec=torch.empty((self.total, 4), dtype=torch.int32, device=dev),
+                    lists=[torch.empty(int(max(c, 0)), dtype=torch.int64, device=dev) for c in cap],
+                    cap=np.ascontiguousarray(np.asarray(cap, dtype=np.int64).reshape(4)),
+                    counts=torch.zeros(4 * self.nfields, dtype=torch.int64, device=dev),
+                    offsets=torch.zeros(4 * (self.nfields + 1), dtype=torch.int64, device=dev),
+                    flags=new_flags(dev))
+
+    def launch(self, values, b):
+        """Enqueues one run on the current stream into the buffers b (no sync)."""
+        _require_gpu(values, "values")
+        if values.numel() != self.total:
+            raise ValueError("values must hold all fields concatenated (%d)" % self.total)
+        lists = b["lists"]
+        _check(lib().dms_batch_run(self.ptr, _ptr(values), _ptr(b["order"]), _ptr(b["rec"]),
+                                   _ptr(lists[0]), _ptr(lists[1]), _ptr(lists[2]), _ptr(lists[3]),
+                                   b["cap"].ctypes.data_as(ctypes.c_void_p), _ptr(b["counts"]),
+                                   _ptr(b["offsets"]), _ptr(self.ws), self.ws.numel(),
+                                   _ptr(b["flags"]), _stream(values)), "dms_batch_run")
+
+    def run(self, values, cap=None, reuse=True):
+        if cap is None and self.bufs is not None and reuse:
+            b = self.bufs
+        else:
+            if cap is None:
+                probe = self._alloc([0, 0, 0, 0])
+                self.launch(values, probe)
+                cap = probe["offsets"].view(4, self.nfields + 1)[:, -1].cpu().numpy()
+            b = self._alloc(cap)
+            self.bufs = b
+        b["flags"].zero_()
+        self.launch(values, b)
+        check_flags(b["flags"])
+        return (b["order"], b["rec"], b["lists"], b["counts"].view(self.nfields, 4),
+                b["offsets"].view(4, self.nfields + 1))
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                lib().dms_batch_destroy(self.ptr)
+                self.ptr = ctypes.c_void_p()
+        except Exception:
+            pass
 
 
 from .autograd import PersistenceD0  # noqa: E402  (torch autograd wrapper)

@@ -10,6 +10,7 @@
 //         written at tile offset + block-scan offset as int64 codes
 //         (max vertex id << 8) | local index.
 #include "dms_common.hpp"
+#include "dms_internal.hpp"
 #include "dms_scan.hpp"
 #include "dms_tables.hpp"
 
@@ -86,55 +87,17 @@ __device__ __forceinline__ int64_t box_vertex(int64_t r, int64_t w0, int64_t w1,
     return i + nx * (j + ny * k);
 }
 
-__global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec, int64_t nbox,
-                                                         uint64_t *__restrict__ tile_counts,
-                                                         int64_t ntiles)
+// Writes the critical cells of one record (counts c, first slots at) as
+// codes base | local index.
+__device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint32_t *c,
+                                            const uint64_t *at, int64_t base, int64_t *crit0,
+                                            int64_t *crit1, int64_t *crit2, int64_t *crit3,
+                                            int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
 {
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    uint32_t c[4] = {0, 0, 0, 0};
-    if (r < nbox) {
-        const uint4 w = rec[r];
-        count_critical((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), c);
-    }
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        uint64_t total;
-        block_exclusive_scan<uint64_t>(c[d], &total);
-        if (threadIdx.x == 0) tile_counts[(int64_t)d * ntiles + blockIdx.x] = total;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) tile_counts[4 * ntiles] = 0;
-}
-
-__global__ __launch_bounds__(kThreads) void k_crit_fill(
-    const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
-    int64_t w0, int64_t w1, int64_t lo0, int64_t lo1, int64_t lo2, int64_t nx, int64_t ny,
-    int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
-    int64_t cap2, int64_t cap3)
-{
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    uint32_t c[4] = {0, 0, 0, 0};
-    uint64_t lo = 0, hi = 0;
-    if (r < nbox) {
-        const uint4 w = rec[r];
-        lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
-        hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
-        count_critical(lo, hi, c);
-    }
-    uint64_t at[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        uint64_t total;
-        const uint64_t ex = block_exclusive_scan<uint64_t>(c[d], &total);
-        at[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles] + ex;
-    }
-    if (r >= nbox || (c[0] | c[1] | c[2] | c[3]) == 0) return;
-    const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
-    const int64_t base = v << 8;
     if (c[0]) {
         if ((int64_t)at[0] < cap0) crit0[at[0]] = base;
         return;  // a minimum has an empty lower star beyond itself
     }
-    // full decode of this record
     const uint32_t low = lower_edges(lo);
     uint32_t crit_e = 0;
     uint64_t head_t = 0, tail_t = 0;
@@ -183,6 +146,52 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill(
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec, int64_t nbox,
+                                                         uint64_t *__restrict__ tile_counts,
+                                                         int64_t ntiles)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint32_t c[4] = {0, 0, 0, 0};
+    if (r < nbox) {
+        const uint4 w = rec[r];
+        count_critical((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), c);
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        uint64_t total;
+        block_exclusive_scan<uint64_t>(c[d], &total);
+        if (threadIdx.x == 0) tile_counts[(int64_t)d * ntiles + blockIdx.x] = total;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) tile_counts[4 * ntiles] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_crit_fill(
+    const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
+    int64_t w0, int64_t w1, int64_t lo0, int64_t lo1, int64_t lo2, int64_t nx, int64_t ny,
+    int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
+    int64_t cap2, int64_t cap3)
+{
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint32_t c[4] = {0, 0, 0, 0};
+    uint64_t lo = 0, hi = 0;
+    if (r < nbox) {
+        const uint4 w = rec[r];
+        lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
+        hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
+        count_critical(lo, hi, c);
+    }
+    uint64_t at[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        uint64_t total;
+        const uint64_t ex = block_exclusive_scan<uint64_t>(c[d], &total);
+        at[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles] + ex;
+    }
+    if (r >= nbox || (c[0] | c[1] | c[2] | c[3]) == 0) return;
+    const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
+    write_codes(lo, hi, c, at, v << 8, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+}
+
 __global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *counts, int64_t cap0,
                               int64_t cap1, int64_t cap2, int64_t cap3, uint32_t *flags)
 {
@@ -197,12 +206,106 @@ __global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *cou
     if (over) atomicOr(flags, (uint32_t)DMS_FLAG_CAPACITY);
 }
 
+
+// Batched fill: records of whole fields concatenated; codes carry the
+// field-local vertex id; the first record of each field publishes the
+// field's first slot in every list.
+__global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
+    const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
+    const int64_t *__restrict__ foff, int nfields, int64_t *fstart, int64_t *crit0, int64_t *crit1,
+    int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
+{
+    __shared__ int64_t so[kMaxBatchFields + 1];
+    for (int i = threadIdx.x; i <= nfields; i += kThreads) so[i] = foff[i];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint32_t c[4] = {0, 0, 0, 0};
+    uint64_t lo = 0, hi = 0;
+    if (r < nbox) {
+        const uint4 w = rec[r];
+        lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
+        hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
+        count_critical(lo, hi, c);
+    }
+    uint64_t at[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        uint64_t total;
+        const uint64_t ex = block_exclusive_scan<uint64_t>(c[d], &total);
+        at[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles] + ex;
+    }
+    if (r >= nbox) return;
+    int f0 = 0, f1 = nfields - 1;
+    while (f0 < f1) {
+        const int mid = (f0 + f1 + 1) >> 1;
+        if (so[mid] <= r) f0 = mid; else f1 = mid - 1;
+    }
+    if (r == so[f0])
+        for (int d = 0; d < 4; ++d) fstart[(int64_t)d * (nfields + 1) + f0] = (int64_t)at[d];
+    if ((c[0] | c[1] | c[2] | c[3]) == 0) return;
+    write_codes(lo, hi, c, at, (r - so[f0]) << 8, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+}
+
+__global__ void k_crit_finish_batch(const uint64_t *offs, int64_t ntiles, int nfields, int64_t *fstart,
+                                    int64_t *counts, int64_t cap0, int64_t cap1, int64_t cap2,
+                                    int64_t cap3, uint32_t *flags)
+{
+    const int64_t cap[4] = {cap0, cap1, cap2, cap3};
+    for (int d = 0; d < 4; ++d) {
+        const int64_t tot = (int64_t)(offs[(int64_t)(d + 1) * ntiles] - offs[(int64_t)d * ntiles]);
+        if (threadIdx.x == 0) {
+            fstart[(int64_t)d * (nfields + 1) + nfields] = tot;
+            if (tot > cap[d]) atomicOr(flags, (uint32_t)DMS_FLAG_CAPACITY);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4 * nfields; i += blockDim.x) {
+        const int f = i / 4, d = i % 4;
+        const int64_t *fs = fstart + (int64_t)d * (nfields + 1);
+        counts[i] = fs[f + 1] - fs[f];
+    }
+}
+
 __global__ void k_crit_empty(int64_t *counts)
 {
     if (threadIdx.x < 4) counts[threadIdx.x] = 0;
 }
 
 }  // namespace
+}  // namespace dms
+
+
+namespace dms {
+
+size_t critical_batch_workspace_size(int64_t n, int nfields)
+{
+    (void)nfields;
+    const int64_t ntiles = (n + kThreads - 1) / kThreads;
+    const int64_t len = 4 * ntiles + 1;
+    return align_up((size_t)len * 8, 256) + scan_partials_bytes(len, 8);
+}
+
+int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, int nfields,
+                          const BatchField *fields, int64_t *const crit[4], const int64_t cap[4],
+                          int64_t *counts, int64_t *offsets, char *ws, uint32_t *flags,
+                          hipStream_t s)
+{
+    (void)fields;
+    const int64_t ntiles = (n + kThreads - 1) / kThreads;
+    const int64_t len = 4 * ntiles + 1;
+    uint64_t *tc = (uint64_t *)ws;
+    uint64_t *partials = (uint64_t *)(ws + align_up((size_t)len * 8, 256));
+    hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
+                       n, tc, ntiles);
+    exclusive_scan<uint64_t>(tc, len, partials, s);
+    hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
+                       (const uint4 *)rec, n, tc, ntiles, foff, nfields, offsets, crit[0], crit[1],
+                       crit[2], crit[3], cap[0], cap[1], cap[2], cap[3]);
+    hipLaunchKernelGGL(k_crit_finish_batch, dim3(1), dim3(256), 0, s, tc, ntiles, nfields, offsets,
+                       counts, cap[0], cap[1], cap[2], cap[3], flags);
+    return launch_status();
+}
+
 }  // namespace dms
 
 extern "C" size_t dms_critical_workspace_size(const int64_t dims[3], const int64_t lo[3],

@@ -17,15 +17,13 @@
 // enter the one-facet queue; entries of the zero queue that get paired are
 // dropped (Robins' lazy deletion gives the same pops).
 #include "dms_common.hpp"
+#include "dms_internal.hpp"
 #include "dms_tables.hpp"
 
 namespace dms {
 namespace {
 
-constexpr int GX = 64, GY = 4, GZ = 1;  // owned vertices per block
-constexpr int kThreads = GX * GY * GZ;
-constexpr int HX = GX + 2, HY = GY + 2, HZ = GZ + 2;
-constexpr int kHalo = HX * HY * HZ;
+constexpr int kThreads = 256;  // vertices per tile (one per thread)
 constexpr int32_t kAbsent = 0x7fffffff;
 constexpr int kSizeBins = 76;  // lower-star sizes 0..75
 
@@ -230,41 +228,52 @@ __device__ void process_vertex(const int32_t *o, int32_t ox, int mmax, const Sha
                      (uint32_t)(rec_hi >> 32));
 }
 
+template <int GX, int GY>
+struct Tile {
+    static_assert(GX * GY == kThreads, "one vertex per thread");
+    static constexpr int HX = GX + 2, HY = GY + 2, HZ = 3;
+    static constexpr int kHalo = HX * HY * HZ;
+};
+
+template <int GX, int GY>
 __device__ __forceinline__ void gather_orders(const int32_t *tile, int c, int32_t *o)
 {
+    using S = Tile<GX, GY>;
 #pragma unroll
     for (int e = 0; e < 14; ++e)
-        o[e] = tile[c + kTables.nb[e][0] + HX * (kTables.nb[e][1] + HY * kTables.nb[e][2])];
+        o[e] = tile[c + kTables.nb[e][0] + S::HX * (kTables.nb[e][1] + S::HY * kTables.nb[e][2])];
 }
 
-// Each block stages the orders of a GX x GY x GZ tile of the owned box plus
-// a one-vertex halo, then assigns its vertices to threads sorted by the size
-// of their lower stars, so that the vertices of a wave need similar numbers
-// of steps (a wave runs as long as its slowest lane).
-__global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict__ order,
-                                                       int64_t nx, int64_t ny, int64_t nz,
-                                                       int64_t lo0, int64_t lo1, int64_t lo2,
-                                                       int64_t w0, int64_t w1, int64_t w2,
-                                                       int64_t bx_count, int64_t by_count,
-                                                       uint4 *__restrict__ rec)
-{
-    __shared__ SharedTables T;
-    __shared__ int32_t tile[kHalo];
-    __shared__ uint32_t bins[kSizeBins];
-    __shared__ uint16_t perm[kThreads];
+struct BlockShared {
+    SharedTables T;
+    uint32_t bins[kSizeBins];
+    uint16_t perm[kThreads];
+};
 
+__device__ __forceinline__ void load_tables(SharedTables &T)
+{
+    const uint32_t *src = (const uint32_t *)&g_tables;
+    uint32_t *dst = (uint32_t *)&T;
+    for (int i = threadIdx.x; i < (int)(sizeof(SharedTables) / 4); i += kThreads) dst[i] = src[i];
+}
+
+// One GX x GY x 1 tile of the owned box [lo, lo + w) of a grid of dims n.
+// Stages the orders of the tile plus a one-vertex halo, then assigns the
+// tile's vertices to threads sorted by the size of their lower stars, so that
+// the vertices of a wave need similar numbers of steps (a wave runs as long as
+// its slowest lane).  Must be entered by the whole block.
+template <int GX, int GY>
+__device__ void gradient_tile(const int32_t *__restrict__ order, int64_t nx, int64_t ny, int64_t nz,
+                              int64_t lo0, int64_t lo1, int64_t lo2, int64_t w0, int64_t w1,
+                              int64_t w2, int64_t bx, int64_t by, int64_t bz,
+                              uint4 *__restrict__ rec, BlockShared &sh, int32_t *tile)
+{
+    using S = Tile<GX, GY>;
     const int tid = threadIdx.x;
-    {
-        const uint32_t *src = (const uint32_t *)&g_tables;
-        uint32_t *dst = (uint32_t *)&T;
-        for (int i = tid; i < (int)(sizeof(SharedTables) / 4); i += kThreads) dst[i] = src[i];
-    }
-    for (int i = tid; i < kSizeBins; i += kThreads) bins[i] = 0;
-    const int64_t b = blockIdx.x;
-    const int64_t bx = b % bx_count, by = (b / bx_count) % by_count, bz = b / (bx_count * by_count);
-    const int64_t x0 = lo0 + bx * GX - 1, y0 = lo1 + by * GY - 1, z0 = lo2 + bz * GZ - 1;
-    for (int i = tid; i < kHalo; i += kThreads) {
-        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+    for (int i = tid; i < kSizeBins; i += kThreads) sh.bins[i] = 0;
+    const int64_t x0 = lo0 + bx * GX - 1, y0 = lo1 + by * GY - 1, z0 = lo2 + bz - 1;
+    for (int i = tid; i < S::kHalo; i += kThreads) {
+        const int hx = i % S::HX, hy = (i / S::HX) % S::HY, hz = i / (S::HX * S::HY);
         const int64_t x = x0 + hx, y = y0 + hy, z = z0 + hz;
         int32_t v = kAbsent;
         if (x >= 0 && y >= 0 && z >= 0 && x < nx && y < ny && z < nz) v = order[x + nx * (y + ny * z)];
@@ -275,20 +284,20 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict
     // lower-star size of the vertex at tile slot tid (0 outside the box)
     int size = 0;
     {
-        const int tx = tid % GX, ty = (tid / GX) % GY, tz = tid / (GX * GY);
-        if (bx * GX + tx < w0 && by * GY + ty < w1 && bz * GZ + tz < w2) {
-            const int c = (tx + 1) + HX * ((ty + 1) + HY * (tz + 1));
+        const int tx = tid % GX, ty = tid / GX;
+        if (bx * GX + tx < w0 && by * GY + ty < w1 && bz < w2) {
+            const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
             int32_t o[14];
-            gather_orders(tile, c, o);
+            gather_orders<GX, GY>(tile, c, o);
             const uint32_t low = lower_mask(o, tile[c]);
             size = 1 + __popc(low) + __popcll(lower_star_tq(low));
         }
     }
-    const uint32_t slot = atomicAdd(&bins[size], 1u);
+    const uint32_t slot = atomicAdd(&sh.bins[size], 1u);
     __syncthreads();
     if (tid < kWave) {  // exclusive scan of the bins by the first wave
-        uint32_t v0 = tid < kSizeBins ? bins[tid] : 0u;
-        uint32_t v1 = tid + kWave < kSizeBins ? bins[tid + kWave] : 0u;
+        const uint32_t v0 = tid < kSizeBins ? sh.bins[tid] : 0u;
+        const uint32_t v1 = tid + kWave < kSizeBins ? sh.bins[tid + kWave] : 0u;
         uint32_t i0 = v0, i1 = v1;
 #pragma unroll
         for (int off = 1; off < kWave; off <<= 1) {
@@ -296,32 +305,139 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict
             if (tid >= off) { i0 += t0; i1 += t1; }
         }
         const uint32_t tot0 = __shfl(i0, kWave - 1);
-        if (tid < kSizeBins) bins[tid] = i0 - v0;
-        if (tid + kWave < kSizeBins) bins[tid + kWave] = tot0 + i1 - v1;
+        if (tid < kSizeBins) sh.bins[tid] = i0 - v0;
+        if (tid + kWave < kSizeBins) sh.bins[tid + kWave] = tot0 + i1 - v1;
     }
     __syncthreads();
-    perm[bins[size] + slot] = (uint16_t)tid;
+    sh.perm[sh.bins[size] + slot] = (uint16_t)tid;
     __syncthreads();
 
-    const int v = perm[tid];
-    const int tx = v % GX, ty = (v / GX) % GY, tz = v / (GX * GY);
-    const int64_t ox_ = bx * GX + tx, oy_ = by * GY + ty, oz_ = bz * GZ + tz;  // box coordinates
+    const int v = sh.perm[tid];
+    const int tx = v % GX, ty = v / GX;
+    const int64_t ox_ = bx * GX + tx, oy_ = by * GY + ty, oz_ = bz;  // box coordinates
     const bool inside = ox_ < w0 && oy_ < w1 && oz_ < w2;
-    const int c = (tx + 1) + HX * ((ty + 1) + HY * (tz + 1));
+    const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
     int32_t o[14];
-    gather_orders(tile, c, o);
+    gather_orders<GX, GY>(tile, c, o);
     const int m = inside ? __popc(lower_mask(o, tile[c])) : 0;
     int mmax = m;
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
     mmax = __builtin_amdgcn_readfirstlane(mmax);
-    if (!inside) return;
-    uint4 r;
-    process_vertex(o, tile[c], mmax, T, r);
-    rec[ox_ + w0 * (oy_ + w1 * oz_)] = r;
+    if (inside) {
+        uint4 r;
+        process_vertex(o, tile[c], mmax, sh.T, r);
+        rec[ox_ + w0 * (oy_ + w1 * oz_)] = r;
+    }
+}
+
+template <int GX, int GY>
+__global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict__ order,
+                                                       int64_t nx, int64_t ny, int64_t nz,
+                                                       int64_t lo0, int64_t lo1, int64_t lo2,
+                                                       int64_t w0, int64_t w1, int64_t w2,
+                                                       int64_t bx_count, int64_t by_count,
+                                                       uint4 *__restrict__ rec)
+{
+    __shared__ BlockShared sh;
+    __shared__ int32_t tile[Tile<GX, GY>::kHalo];
+    load_tables(sh.T);
+    const int64_t b = blockIdx.x;
+    const int64_t bx = b % bx_count, by = (b / bx_count) % by_count, bz = b / (bx_count * by_count);
+    gradient_tile<GX, GY>(order, nx, ny, nz, lo0, lo1, lo2, w0, w1, w2, bx, by, bz, rec, sh, tile);
+}
+
+// Batched form: many whole fields, concatenated; a persistent grid walks the
+// (field, tile) list, field f owning tiles [tile_start[f], tile_start[f+1]).
+template <int GX, int GY>
+__global__ __launch_bounds__(kThreads) void k_gradient_batch(const int32_t *__restrict__ order,
+                                                             const BatchField *__restrict__ fields,
+                                                             int nfields, const int64_t *tile_start,
+                                                             uint4 *__restrict__ rec)
+{
+    __shared__ BlockShared sh;
+    __shared__ int32_t tile[Tile<GX, GY>::kHalo];
+    __shared__ int64_t tstart[kMaxBatchFields + 1];
+    load_tables(sh.T);
+    for (int i = threadIdx.x; i <= nfields; i += kThreads) tstart[i] = tile_start[i];
+    __syncthreads();
+    const int64_t total = tstart[nfields];
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = nfields - 1;  // last field with tstart <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tstart[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const BatchField F = fields[lo];
+        const int64_t bxc = (F.n[0] + GX - 1) / GX, byc = (F.n[1] + GY - 1) / GY;
+        const int64_t k = t - tstart[lo];
+        const int64_t bx = k % bxc, by = (k / bxc) % byc, bz = k / (bxc * byc);
+        gradient_tile<GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1], F.n[2],
+                              bx, by, bz, rec + F.off, sh, tile);
+        __syncthreads();  // the next tile reuses the shared buffers
+    }
 }
 
 }  // namespace
+}  // namespace dms
+
+namespace dms {
+
+int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
+                    const int64_t *hi, uint32_t *rec, hipStream_t s)
+{
+    const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
+    if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
+    const int gx = kTileX[variant], gy = kThreads / gx;
+    const int64_t bxc = (w0 + gx - 1) / gx, byc = (w1 + gy - 1) / gy;
+    const int64_t blocks = bxc * byc * w2;
+    if (blocks > 2147483647LL) return DMS_E_SIZE;
+#define DMS_LAUNCH(GXV)                                                                              \
+    hipLaunchKernelGGL((k_gradient<GXV, kThreads / GXV>), dim3((unsigned)blocks), dim3(kThreads), 0, s, \
+                       order, dims[0], dims[1], dims[2], lo[0], lo[1], lo[2], w0, w1, w2, bxc, byc,  \
+                       (uint4 *)rec)
+    switch (variant) {
+    case 0: DMS_LAUNCH(64); break;
+    case 1: DMS_LAUNCH(32); break;
+    default: DMS_LAUNCH(16); break;
+    }
+#undef DMS_LAUNCH
+    return launch_status();
+}
+
+int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
+                          const int64_t *tile_start, int64_t total_tiles, uint32_t *rec, int grid,
+                          hipStream_t s)
+{
+    if (total_tiles == 0) return DMS_OK;
+    const unsigned g = (unsigned)(total_tiles < grid ? total_tiles : grid);
+#define DMS_LAUNCH(GXV)                                                                          \
+    hipLaunchKernelGGL((k_gradient_batch<GXV, kThreads / GXV>), dim3(g), dim3(kThreads), 0, s,  \
+                       order, fields, nfields, tile_start, (uint4 *)rec)
+    switch (variant) {
+    case 0: DMS_LAUNCH(64); break;
+    case 1: DMS_LAUNCH(32); break;
+    default: DMS_LAUNCH(16); break;
+    }
+#undef DMS_LAUNCH
+    return launch_status();
+}
+
+int gradient_batch_grid(int variant)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e;
+    switch (variant) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<64, 4>, kThreads, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<32, 8>, kThreads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<16, 16>, kThreads, 0); break;
+    }
+    if (e != hipSuccess || per < 1) per = 1;
+    return cus * per;
+}
+
 }  // namespace dms
 
 extern "C" int dms_discrete_gradient(const int32_t *order, const int64_t dims[3], const int64_t lo[3],
@@ -333,11 +449,5 @@ extern "C" int dms_discrete_gradient(const int32_t *order, const int64_t dims[3]
     const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
     if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
     if (!order || !rec) return DMS_E_ARG;
-    const int64_t bxc = (w0 + GX - 1) / GX, byc = (w1 + GY - 1) / GY, bzc = (w2 + GZ - 1) / GZ;
-    const int64_t blocks = bxc * byc * bzc;
-    if (blocks > 2147483647LL) return DMS_E_SIZE;
-    hipLaunchKernelGGL(k_gradient, dim3((unsigned)blocks), dim3(kThreads), 0, (hipStream_t)stream,
-                       order, dims[0], dims[1], dims[2], lo[0], lo[1], lo[2], w0, w1, w2, bxc, byc,
-                       (uint4 *)rec);
-    return launch_status();
+    return launch_gradient(0, order, dims, lo, hi, rec, (hipStream_t)stream);
 }

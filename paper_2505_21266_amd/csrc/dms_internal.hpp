@@ -1,0 +1,42 @@
+// dms_internal.hpp -- launch helpers shared by the single-field entry points
+// and the batched plan.
+#pragma once
+#include "dms_common.hpp"
+
+namespace dms {
+
+// Largest number of fields in one batch (their tables live in LDS).
+constexpr int kMaxBatchFields = 1024;
+
+// One field of a batch: dims (x, y, z) and its offset in the concatenated
+// arrays (values, orders and records alike).
+struct BatchField {
+    int64_t n[3];
+    int64_t off;
+};
+
+// Gradient tile shapes (x extent; 256 threads per tile): 64x4, 32x8, 16x16.
+constexpr int kGradVariants = 3;
+constexpr int kTileX[kGradVariants] = {64, 32, 16};
+
+int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
+                    const int64_t *hi, uint32_t *rec, hipStream_t s);
+int gradient_batch_grid(int variant);  // persistent grid size (CUs x resident blocks)
+int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
+                          const int64_t *tile_start, int64_t total_tiles, uint32_t *rec, int grid,
+                          hipStream_t s);
+
+// Batched order: values of all fields concatenated (float32); the field of
+// element i is the f with foff[f] <= i < foff[f + 1] (foff on the device).
+size_t order_batch_workspace_size(int64_t n);
+int launch_order_batch(const float *values, int64_t n, const int64_t *foff, int nfields,
+                       int32_t *order, char *ws, uint32_t *flags, hipStream_t s);
+
+// Batched extraction over concatenated whole-field records.
+size_t critical_batch_workspace_size(int64_t n, int nfields);
+int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, int nfields,
+                          const BatchField *fields, int64_t *const crit[4], const int64_t cap[4],
+                          int64_t *counts, int64_t *offsets, char *ws, uint32_t *flags,
+                          hipStream_t s);
+
+}  // namespace dms

@@ -16,6 +16,7 @@
 // are in element order); ranks inside a wave come from ballot-based digit
 // matching, ranks across waves from per-wave digit counts in LDS.
 #include "dms_common.hpp"
+#include "dms_internal.hpp"
 #include "dms_scan.hpp"
 
 namespace dms {
@@ -27,30 +28,31 @@ constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;
 constexpr int kRadix = 256;
 
-template <typename V>
-struct KeyT;
-template <>
-struct KeyT<float> {
-    using K = uint32_t;
-    static constexpr int kPasses = 4;
-};
-template <>
-struct KeyT<double> {
-    using K = uint64_t;
-    static constexpr int kPasses = 8;
-};
+// Key types: uint32_t for float32, uint64_t for float64 and for batches
+// (field index in bits 32..39 above the float32 key).
+constexpr int kBatchPasses = 5;
+
+// field of element i: the last f with foff[f] <= i (binary search)
+__device__ __forceinline__ int field_of(const int64_t *foff, int nfields, int64_t i)
+{
+    int lo = 0, hi = nfields - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (foff[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 __device__ __forceinline__ int64_t elem_index(int64_t tile, int wave, int k, int lane)
 {
     return tile * kTile + (int64_t)wave * (kItems * kWave) + k * kWave + lane;
 }
 
-template <typename V, bool kFirst>
-__device__ __forceinline__ typename KeyT<V>::K load_key(const void *src, int64_t i, bool &nan)
+template <typename V, typename K, bool kFirst>
+__device__ __forceinline__ K load_key(const void *src, int64_t i, bool &nan)
 {
-    using K = typename KeyT<V>::K;
     if constexpr (kFirst) {
-        return key_of(((const V *)src)[i], nan);
+        return (K)key_of(((const V *)src)[i], nan);
     } else {
         nan = false;
         return ((const K *)src)[i];
@@ -59,12 +61,11 @@ __device__ __forceinline__ typename KeyT<V>::K load_key(const void *src, int64_t
 
 // (1) per-tile histogram of the digit at `shift`; counts is digit-major:
 // counts[d * ntiles + tile].
-template <typename V, bool kFirst>
+template <typename V, typename K, bool kFirst>
 __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t n, int shift,
                                                         uint32_t *counts, int64_t ntiles,
                                                         uint32_t *flags)
 {
-    using K = typename KeyT<V>::K;
     __shared__ uint32_t hist[kWaves][kRadix];
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     for (int i = tid; i < kWaves * kRadix; i += kThreads) (&hist[0][0])[i] = 0;
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t
         uint32_t d = 0;
         if (valid) {
             bool nan;
-            K key = load_key<V, kFirst>(src, i, nan);
+            K key = load_key<V, K, kFirst>(src, i, nan);
             nan_any |= nan;
             d = (uint32_t)(key >> shift) & (kRadix - 1);
         }
@@ -94,14 +95,16 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t
 
 // (3) stable scatter of one tile by the digit at `shift`.  offsets holds the
 // scanned counts (global start of digit d in tile `tile`).
-template <typename V, bool kFirst, bool kLast>
+// foff (nfields + 1 offsets) is non-null for batches: the first pass puts
+// the field index above the value key, the last writes order = position
+// minus the field's offset.
+template <typename V, typename K, bool kFirst, bool kLast>
 __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uint32_t *src_ids,
                                                       int64_t n, int shift,
                                                       const uint32_t *offsets, int64_t ntiles,
-                                                      typename KeyT<V>::K *dst_keys,
-                                                      uint32_t *dst_ids, int32_t *order)
+                                                      K *dst_keys, uint32_t *dst_ids, int32_t *order,
+                                                      const int64_t *foff, int nfields)
 {
-    using K = typename KeyT<V>::K;
     __shared__ uint32_t whist[kWaves][kRadix];
     __shared__ uint32_t digit_start[kRadix];
     __shared__ uint32_t gbase[kRadix];
@@ -125,7 +128,10 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
         id[k] = 0;
         if (valid) {
             bool nan;
-            key[k] = load_key<V, kFirst>(src, i, nan);
+            key[k] = load_key<V, K, kFirst>(src, i, nan);
+            if constexpr (kFirst && sizeof(K) == 8) {
+                if (foff) key[k] |= (K)field_of(foff, nfields, i) << 32;
+            }
             id[k] = kFirst ? (uint32_t)i : src_ids[i];
             d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
         }
@@ -176,7 +182,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
             // that in bounds
             if ((int64_t)g < n && (int64_t)who < n) {
                 if (kLast) {
-                    order[who] = (int32_t)g;
+                    int64_t base = 0;
+                    if constexpr (sizeof(K) == 8) {
+                        if (foff) base = foff[(int)(kk >> 32)];
+                    }
+                    order[who] = (int32_t)((int64_t)g - base);
                 } else {
                     dst_keys[g] = kk;
                     dst_ids[g] = who;
@@ -190,10 +200,9 @@ struct OrderLayout {
     size_t keys0, keys1, ids0, ids1, counts, partials, total;
 };
 
-template <typename V>
+template <typename K>
 OrderLayout order_layout(int64_t n)
 {
-    using K = typename KeyT<V>::K;
     const int64_t ntiles = (n + kTile - 1) / kTile;
     const int64_t clen = ntiles * kRadix;
     OrderLayout L{};
@@ -208,51 +217,59 @@ OrderLayout order_layout(int64_t n)
     return L;
 }
 
-template <typename V>
-int run_order(const void *values, int64_t n, int32_t *order, char *ws, uint32_t *flags,
-              hipStream_t s)
+template <typename V, typename K>
+int run_order(const void *values, int64_t n, int passes, int32_t *order, char *ws, uint32_t *flags,
+              const int64_t *foff, int nfields, hipStream_t s)
 {
-    using K = typename KeyT<V>::K;
-    const OrderLayout L = order_layout<V>(n);
+    const OrderLayout L = order_layout<K>(n);
     const int64_t ntiles = (n + kTile - 1) / kTile;
     K *keys[2] = {(K *)(ws + L.keys0), (K *)(ws + L.keys1)};
     uint32_t *ids[2] = {(uint32_t *)(ws + L.ids0), (uint32_t *)(ws + L.ids1)};
     uint32_t *counts = (uint32_t *)(ws + L.counts);
     uint32_t *partials = (uint32_t *)(ws + L.partials);
-    const int passes = KeyT<V>::kPasses;
     const dim3 grid((unsigned)ntiles), block(kThreads);
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         const void *src = p == 0 ? values : (const void *)keys[(p - 1) & 1];
         const uint32_t *sids = p == 0 ? nullptr : ids[(p - 1) & 1];
         if (p == 0)
-            hipLaunchKernelGGL((k_tile_hist<V, true>), grid, block, 0, s, src, n, shift, counts,
+            hipLaunchKernelGGL((k_tile_hist<V, K, true>), grid, block, 0, s, src, n, shift, counts,
                                ntiles, flags);
         else
-            hipLaunchKernelGGL((k_tile_hist<V, false>), grid, block, 0, s, src, n, shift, counts,
+            hipLaunchKernelGGL((k_tile_hist<V, K, false>), grid, block, 0, s, src, n, shift, counts,
                                ntiles, flags);
         exclusive_scan<uint32_t>(counts, ntiles * kRadix, partials, s);
         if (p == 0)
-            hipLaunchKernelGGL((k_scatter<V, true, false>), grid, block, 0, s, src, sids, n, shift,
-                               counts, ntiles, keys[p & 1], ids[p & 1], order);
+            hipLaunchKernelGGL((k_scatter<V, K, true, false>), grid, block, 0, s, src, sids, n, shift,
+                               counts, ntiles, keys[p & 1], ids[p & 1], order, foff, nfields);
         else if (p == passes - 1)
-            hipLaunchKernelGGL((k_scatter<V, false, true>), grid, block, 0, s, src, sids, n, shift,
-                               counts, ntiles, keys[p & 1], ids[p & 1], order);
+            hipLaunchKernelGGL((k_scatter<V, K, false, true>), grid, block, 0, s, src, sids, n, shift,
+                               counts, ntiles, keys[p & 1], ids[p & 1], order, foff, nfields);
         else
-            hipLaunchKernelGGL((k_scatter<V, false, false>), grid, block, 0, s, src, sids, n, shift,
-                               counts, ntiles, keys[p & 1], ids[p & 1], order);
+            hipLaunchKernelGGL((k_scatter<V, K, false, false>), grid, block, 0, s, src, sids, n, shift,
+                               counts, ntiles, keys[p & 1], ids[p & 1], order, foff, nfields);
     }
     return launch_status();
 }
 
 }  // namespace
+
+size_t order_batch_workspace_size(int64_t n) { return order_layout<uint64_t>(n > 0 ? n : 1).total; }
+
+int launch_order_batch(const float *values, int64_t n, const int64_t *foff, int nfields,
+                       int32_t *order, char *ws, uint32_t *flags, hipStream_t s)
+{
+    if (n == 0) return DMS_OK;
+    return run_order<float, uint64_t>(values, n, kBatchPasses, order, ws, flags, foff, nfields, s);
+}
+
 }  // namespace dms
 
 extern "C" size_t dms_order_workspace_size(int64_t n, int dtype)
 {
     if (n <= 0) return 256;
-    if (dtype == DMS_F32) return dms::order_layout<float>(n).total;
-    if (dtype == DMS_F64) return dms::order_layout<double>(n).total;
+    if (dtype == DMS_F32) return dms::order_layout<uint32_t>(n).total;
+    if (dtype == DMS_F64) return dms::order_layout<uint64_t>(n).total;
     return 0;
 }
 
@@ -266,6 +283,8 @@ extern "C" int dms_order(const void *values, int dtype, int64_t n, int32_t *orde
     if (!workspace || workspace_bytes < dms_order_workspace_size(n, dtype)) return DMS_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (dtype == DMS_F32)
-        return dms::run_order<float>(values, n, order, (char *)workspace, dev_flags, s);
-    return dms::run_order<double>(values, n, order, (char *)workspace, dev_flags, s);
+        return dms::run_order<float, uint32_t>(values, n, 4, order, (char *)workspace, dev_flags,
+                                               nullptr, 0, s);
+    return dms::run_order<double, uint64_t>(values, n, 8, order, (char *)workspace, dev_flags, nullptr,
+                                            0, s);
 }
