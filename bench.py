@@ -37,7 +37,10 @@ def parse():
     ap.add_argument("--owned", type=int, default=1024, help="owned vertices per side")
     ap.add_argument("--bumps", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and differentiable lines")
     ap.add_argument("--cpu-planes", type=int, default=12, help="owned z-planes in the oracle sample")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
@@ -71,6 +74,85 @@ def cpu_baseline(field, lo, hi, planes):
     }
 
 
+def bench_batched(dev, reps):
+    """96 float32 fields with sides U{32..256} per axis (half white noise, half
+    16-Gaussian mixtures): one captured graph per batch, timed over replays."""
+    import torch
+
+    import paper_2505_21266_amd as dms
+    from paper_2505_21266_amd import inputs
+    fields, sides = inputs.config4()
+    vals = torch.from_numpy(np.concatenate([f.reshape(-1) for f in fields])).to(dev)
+    del fields
+    b = dms.Batch([tuple(int(x) for x in s) for s in sides], tune=True)
+    b.run(vals)  # tunes the tile shape, then captures the graph
+    bufs = b.bufs
+    for _ in range(2):
+        b.launch(vals, bufs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.launch(vals, bufs)
+    e1.record()
+    torch.cuda.synchronize()
+    if int(bufs["flags"].item()) != 0:
+        raise RuntimeError("batched run set device flags")
+    ms = e0.elapsed_time(e1) / reps
+    return {"fields": b.nfields, "vertices": b.total, "ms_per_batch": round(ms, 3),
+            "fields_per_s": round(b.nfields / (ms / 1e3), 1),
+            "gvertices_per_s": round(b.total / (ms / 1e3) / 1e9, 3),
+            "tile_variant": ["64x4", "32x8", "16x16"][b.variant], "replays": reps}
+
+
+def bench_differentiable(dev, reps):
+    """128^3 float64 field (16 Gaussians + 1e-4 noise, min gap 1e-9): GPU
+    forward (order, gradient, extraction), host D0 pairing, GPU backward."""
+    import torch
+
+    import paper_2505_21266_amd as dms
+    from paper_2505_21266_amd import inputs
+    f = inputs.config5()
+    x = torch.from_numpy(f).to(dev)
+    dims = dms.dims_of(x)
+    n = x.numel()
+    o = dms.order(x)
+    rec = dms.discrete_gradient(o)
+    lists, counts = dms.critical_simplices(rec, dims)
+    cap = counts.cpu().numpy()
+    torch.cuda.synchronize()
+    fwd, host, bwd = [], [], []
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        o = dms.order(x, check=False)
+        rec = dms.discrete_gradient(o)
+        lists, counts = dms.critical_simplices(rec, dims, cap=cap)
+        e[1].record()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pe, pm = dms.d0_pairs_host(rec.cpu().numpy(), o.cpu().numpy().reshape(-1), dims,
+                                   lists[1].cpu().numpy())
+        t1 = time.perf_counter()
+        dc = torch.from_numpy(pe).to(dev)
+        bc = torch.from_numpy(pm).to(dev) << 8
+        flat = x.reshape(-1)
+        pers = flat[dc >> 8] - flat[bc >> 8]
+        keep = (pers < 0.05).double()
+        gd = (2.0 * pers * keep).contiguous()
+        gb = (-2.0 * pers * keep).contiguous()
+        e[2].record()
+        dms.gradient_backward(bc, dc, gb, gd, n)
+        e[3].record()
+        torch.cuda.synchronize()
+        fwd.append(e[0].elapsed_time(e[1]))
+        host.append((t1 - t0) * 1e3)
+        bwd.append(e[2].elapsed_time(e[3]))
+    return {"vertices": n, "pairs": int(pe.size), "forward_gpu_ms": round(float(np.median(fwd)), 3),
+            "host_d0_ms": round(float(np.median(host)), 3),
+            "backward_gpu_ms": round(float(np.median(bwd)), 4), "reps": reps}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -84,6 +166,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * (1 << 18), dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_gen = time.perf_counter()
     field, lo, hi = inputs.config3(args.owned, args.bumps)
     t_gen = time.perf_counter() - t_gen
@@ -165,6 +253,11 @@ def main():
         "roofline": roofline,
         "input_gen_s": round(t_gen, 1),
     }
+    del values, order_t, rec, lists
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        out["batched"] = bench_batched(dev, max(args.steps, 3))
+        out["differentiable"] = bench_differentiable(dev, max(args.steps, 3))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(field, lo, hi, min(args.cpu_planes, args.owned))
     print(json.dumps(out), flush=True)

@@ -111,7 +111,7 @@ __device__ __forceinline__ uint64_t lower_star_tq(uint32_t low)
 // second set critical.  "Smallest" is a bit-sliced minimum over key planes:
 // plane b holds the cells that contain the neighbour of rank b, and the key
 // of a cell is the integer with those bits (Section 2.1 comparison).
-__device__ void process_vertex(const int32_t *o, int32_t ox, int mmax, const SharedTables &T,
+__device__ __forceinline__ void process_vertex(const int32_t *o, int32_t ox, int mmax, const SharedTables &T,
                                uint4 &out)
 {
     const uint32_t low = lower_mask(o, ox);
@@ -263,7 +263,7 @@ __device__ __forceinline__ void load_tables(SharedTables &T)
 // the vertices of a wave need similar numbers of steps (a wave runs as long as
 // its slowest lane).  Must be entered by the whole block.
 template <int GX, int GY>
-__device__ void gradient_tile(const int32_t *__restrict__ order, int64_t nx, int64_t ny, int64_t nz,
+__device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order, int64_t nx, int64_t ny, int64_t nz,
                               int64_t lo0, int64_t lo1, int64_t lo2, int64_t w0, int64_t w1,
                               int64_t w2, int64_t bx, int64_t by, int64_t bz,
                               uint4 *__restrict__ rec, BlockShared &sh, int32_t *tile)
