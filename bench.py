@@ -102,7 +102,7 @@ def bench_batched(dev, reps):
     return {"fields": b.nfields, "vertices": b.total, "ms_per_batch": round(ms, 3),
             "fields_per_s": round(b.nfields / (ms / 1e3), 1),
             "gvertices_per_s": round(b.total / (ms / 1e3) / 1e9, 3),
-            "tile_variant": ["64x4", "32x8", "16x16"][b.variant], "replays": reps}
+            "tile_variant": ["64x16", "32x32", "16x64"][b.variant], "replays": reps}
 
 
 def bench_differentiable(dev, reps):

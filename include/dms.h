@@ -15,7 +15,11 @@
  *    grid outside it are ghosts (Section 2.2): read, never processed.
  *  - Array arguments are DEVICE pointers owned by the caller unless marked
  *    [host].  Calls never allocate, free or synchronise; they enqueue work on
- *    `stream` (a hipStream_t, NULL = the default stream) and return.
+ *    `stream` (a hipStream_t, NULL = the default stream) and return.  One
+ *    exception: the first dms_discrete_gradient (or dms_batch_create) on a
+ *    device fills a constant 10 MB device table (the records of all lower
+ *    stars whose lower neighbours are one of each opposite pair) and waits
+ *    for it once.
  *  - Argument errors are returned synchronously as a dms_status and nothing
  *    is enqueued.  Data-dependent conditions found on the device are OR-ed
  *    into *dev_flags (a device uint32 the caller zeroes), read after a sync.
@@ -103,8 +107,9 @@ int dms_order(const void *values, int dtype, int64_t n, int32_t *order, void *wo
  * its three edges are, critical unless a triangle field names it.
  * order: int32 of the whole grid (dims), a permutation of 0..n-1 or any
  * injective int32 labelling with the same relative order (values must be
- * < 2^31 - 1).  Errors: DMS_E_ARG (null pointer, dims < 1, box outside the
- * grid or empty is allowed and does nothing), DMS_E_SIZE, DMS_E_HIP.
+ * < 2^31 - 1).  An empty box is allowed and enqueues nothing.
+ * Errors: DMS_E_ARG (null pointer, dims < 1, box outside the grid),
+ * DMS_E_SIZE, DMS_E_HIP.
  * -------------------------------------------------------------------------- */
 int dms_discrete_gradient(const int32_t *order, const int64_t dims[3], const int64_t lo[3],
                           const int64_t hi[3], uint32_t *rec, void *stream);
@@ -201,7 +206,7 @@ int dms_batch_create(const int64_t *dims, int nfields, int dtype, int tune, cons
                      dms_batch **out);
 size_t dms_batch_workspace_size(const dms_batch *batch);
 int64_t dms_batch_total(const dms_batch *batch);   /* vertices in all fields */
-int dms_batch_variant(const dms_batch *batch);     /* chosen gradient tile shape: 0 64x4, 1 32x8, 2 16x16 */
+int dms_batch_variant(const dms_batch *batch);     /* chosen gradient tile shape: 0 64x16, 1 32x32, 2 16x64 */
 int dms_batch_run(dms_batch *batch, const void *values, int32_t *order, uint32_t *rec, int64_t *crit0,
                   int64_t *crit1, int64_t *crit2, int64_t *crit3, const int64_t cap[4],
                   int64_t *counts, int64_t *offsets, void *workspace, size_t workspace_bytes,

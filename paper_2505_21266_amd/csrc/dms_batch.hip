@@ -179,7 +179,7 @@ extern "C" int dms_batch_create(const int64_t *dims, int nfields, int dtype, int
               hipMemcpy(b->d_fields, hf.data(), sizeof(dms::BatchField) * nfields, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(b->d_off, b->off.data(), sizeof(int64_t) * (nfields + 1), hipMemcpyHostToDevice) == hipSuccess;
     for (int v = 0; ok && v < dms::kGradVariants; ++v) {
-        const int gx = dms::kTileX[v], gy = 256 / gx;
+        const int gx = dms::kTileX[v], gy = dms::kTileVertsPerBlock / gx;
         ts[0] = 0;
         for (int f = 0; f < nfields; ++f) {
             const int64_t *d = dims + 3 * f;
@@ -189,7 +189,8 @@ extern "C" int dms_batch_create(const int64_t *dims, int nfields, int dtype, int
         ok = hipMalloc(&b->d_tiles[v], sizeof(int64_t) * (nfields + 1)) == hipSuccess &&
              hipMemcpy(b->d_tiles[v], ts.data(), sizeof(int64_t) * (nfields + 1), hipMemcpyHostToDevice) == hipSuccess;
     }
-    ok = ok && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess &&
+         dms::ensure_regular_table(b->cap_stream) == DMS_OK;
     if (!ok) {
         dms_batch_destroy(b);
         return DMS_E_HIP;

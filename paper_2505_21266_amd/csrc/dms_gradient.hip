@@ -16,6 +16,8 @@
 // Readings: "unpaired" = neither paired nor critical; only unpaired cells
 // enter the one-facet queue; entries of the zero queue that get paired are
 // dropped (Robins' lazy deletion gives the same pops).
+#include <atomic>
+
 #include "dms_common.hpp"
 #include "dms_internal.hpp"
 #include "dms_tables.hpp"
@@ -23,9 +25,10 @@
 namespace dms {
 namespace {
 
-constexpr int kThreads = 256;  // vertices per tile (one per thread)
+constexpr int kThreads = 256;      // threads per block
+constexpr int kTileVerts = 1024;  // vertices per tile (4 per thread)
 constexpr int32_t kAbsent = 0x7fffffff;
-constexpr int kSizeBins = 76;  // lower-star sizes 0..75
+constexpr int kSizeBins = 77;  // keys 1 + lower-star size (1..75); bin 76 stays empty
 
 // Star cells other than x and the edges: triangles t -> bit t, tets q -> bit
 // 36 + q of a 64-bit mask ("TQ space").
@@ -162,9 +165,43 @@ __device__ __forceinline__ void process_vertex(const int32_t *o, int32_t ox, int
     }
     for (int step = 0; step < 80; ++step) {
         const uint64_t one = ftq & cnt.b0 & ~cnt.b1;
-        const bool pair_mode = one != 0;
-        uint64_t S = pair_mode ? one : (ftq & ~cnt.b0 & ~cnt.b1);
-        if (!pair_mode && S == 0 && fr == 0) break;
+        if (one) {
+            // pair the smallest cell with one unpaired facet with that facet
+            uint64_t S = one;
+#pragma unroll
+            for (int b = 13; b >= 0; --b) {
+                if (b < mmax) {
+                    const uint64_t z = S & nkp[b];
+                    S = z ? z : S;
+                }
+            }
+            const int a = __ffsll((unsigned long long)S) - 1;
+            const uint64_t fa = T.facet[a];
+            uint64_t D;
+            if (a < 36) {  // triangle a takes its only unpaired edge e
+                const int e = __ffs((uint32_t)fa & fe) - 1;
+                fe &= ~(1u << e);
+                fr &= ~(1u << nib(rank_of, e));
+                const uint32_t ab = T.tri_ab[a], sl = T.tri_slot[a];
+                const uint32_t slot = (int)(ab & 15u) == e ? (sl & 15u) : (sl >> 4);
+                rec_lo |= (uint64_t)(3u + slot) << (4 * e);
+                D = (T.cont[e] & kTriBits) | T.cofacet[a];
+            } else {  // tet a takes its only unpaired triangle t
+                const int t = __ffsll((unsigned long long)(fa & ftq)) - 1;
+                ftq &= ~(1ull << t);
+                D = T.cofacet[t];
+                const uint64_t v = T.tri_tet0[t] == a - 36 ? 1u : 2u;
+                const int bit = 56 + 2 * t;
+                if (bit < 64) rec_lo |= v << bit; else rec_hi |= v << (bit - 64);
+            }
+            ftq &= ~(1ull << a);
+            cnt.dec(D);
+            continue;
+        }
+        // no cell has exactly one unpaired facet: the smallest unpaired edge or
+        // cell without unpaired facets is critical
+        uint64_t S = ftq & ~cnt.b0 & ~cnt.b1;
+        if (S == 0 && fr == 0) break;
 #pragma unroll
         for (int b = 13; b >= 0; --b) {
             if (b < mmax) {
@@ -173,64 +210,81 @@ __device__ __forceinline__ void process_vertex(const int32_t *o, int32_t ox, int
             }
         }
         const bool have_a = S != 0;
-        const int a = have_a ? __ffsll((unsigned long long)S) - 1 : 0;  // smallest TQ cell
-        const bool is_tri = a < 36;
-        // top rank of cell a (for comparing with the smallest edge)
-        int top;
-        if (is_tri) {
-            const uint32_t ab = T.tri_ab[a];
-            top = max(nib(rank_of, ab & 15u), nib(rank_of, ab >> 4));
-        } else {
-            const int q = a - 36;
-            top = max(max(nib(rank_of, T.tet_abc[q][0]), nib(rank_of, T.tet_abc[q][1])),
-                      nib(rank_of, T.tet_abc[q][2]));
-        }
+        const int a = have_a ? __ffsll((unsigned long long)S) - 1 : 0;
+        bool edge_wins = fr != 0 && !have_a;
         const int re = fr ? __ffs(fr) - 1 : 31;
-        // an unpaired edge is smaller than cell a iff its rank is <= a's top rank
-        const bool edge_wins = !pair_mode && fr != 0 && (!have_a || re <= top);
-        const uint64_t fa = T.facet[a];
-        const uint64_t cof_a = T.cofacet[a];
-
-        uint64_t D = 0;  // cells losing an unpaired facet in this step
-        // the edge that stops being unpaired, if any: a critical edge, or the
-        // only unpaired edge of a triangle being paired
-        int e = -1;
-        uint32_t ev = 0;
+        if (fr != 0 && have_a) {
+            // the edge of rank re is smaller iff re <= the top rank of cell a
+            int top;
+            if (a < 36) {
+                const uint32_t ab = T.tri_ab[a];
+                top = max(nib(rank_of, ab & 15u), nib(rank_of, ab >> 4));
+            } else {
+                const int q = a - 36;
+                top = max(max(nib(rank_of, T.tet_abc[q][0]), nib(rank_of, T.tet_abc[q][1])),
+                          nib(rank_of, T.tet_abc[q][2]));
+            }
+            edge_wins = re <= top;
+        }
         if (edge_wins) {
-            e = nib(nb_at, re);
-            ev = 2;
-        } else if (pair_mode && is_tri) {
-            e = __ffs((uint32_t)fa & fe) - 1;
-            const uint32_t ab = T.tri_ab[a], sl = T.tri_slot[a];
-            ev = 3u + ((int)(ab & 15u) == e ? (sl & 15u) : (sl >> 4));
-        }
-        if (e >= 0) {
+            const int e = nib(nb_at, re);
             fe &= ~(1u << e);
-            fr &= ~(1u << nib(rank_of, e));
-            rec_lo |= (uint64_t)ev << (4 * e);
-            D |= T.cont[e] & kTriBits;
-        }
-        if (!edge_wins) {  // cell a stops being unpaired (critical or paired as head)
+            fr &= ~(1u << re);
+            rec_lo |= 2ull << (4 * e);
+            cnt.dec(T.cont[e] & kTriBits);
+        } else {
             ftq &= ~(1ull << a);
-            D |= cof_a;
+            cnt.dec(T.cofacet[a]);
         }
-        if (pair_mode && !is_tri) {  // a tet takes its only unpaired triangle t
-            const int t = __ffsll((unsigned long long)(fa & ftq)) - 1;
-            ftq &= ~(1ull << t);
-            D |= T.cofacet[t];
-            const uint64_t v = T.tri_tet0[t] == a - 36 ? 1u : 2u;
-            const int bit = 56 + 2 * t;
-            if (bit < 64) rec_lo |= v << bit; else rec_hi |= v << (bit - 64);
-        }
-        cnt.dec(D);
     }
     out = make_uint4((uint32_t)rec_lo, (uint32_t)(rec_lo >> 32), (uint32_t)rec_hi,
                      (uint32_t)(rec_hi >> 32));
 }
 
+// ---------------------------------------------------------------------------
+// Antipodal-regular vertices.  Neighbour e and neighbour 13 - e are opposite
+// offsets.  When exactly one of each of the 7 opposite pairs precedes x (the
+// common case of a smooth field: the lower link is a hemisphere), L(x) is
+// fixed by which member of each pair is lower (7 bits) and by the order of
+// those 7 neighbours (a permutation of 7).  Robins' result for all 128 x 5040
+// such configurations is computed once per device by process_vertex itself
+// and kept in a device table; such vertices then cost a table lookup.
+constexpr int kPerm7 = 5040;
+constexpr int kRegular = 128 * kPerm7;
+__device__ uint4 g_regular[kRegular];
+
+// 7-bit mask: bit i set when the lower member of pair i is neighbour 13 - i;
+// returns false unless exactly one member of every pair is lower.
+__device__ __forceinline__ bool regular_pattern(uint32_t low, uint32_t &side)
+{
+    const uint32_t rev = __brev(low) >> 18;  // bit e -> bit 13 - e
+    side = (low >> 7) & 0x7fu;               // members 7..13, as bits of 13 - e
+    side = __brev(side) >> 25;               // bit (13 - e) - 7 -> bit e' for pair index
+    return ((low ^ rev) & 0x7fu) == 0x7fu;
+}
+
+// Table index of a regular vertex: side pattern x 5040 + Lehmer code of the
+// order of the 7 lower neighbours taken by pair index.
+__device__ __forceinline__ uint32_t regular_index(const int32_t *o, uint32_t side)
+{
+    int32_t v[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) v[i] = ((side >> i) & 1u) ? o[13 - i] : o[i];
+    const uint32_t fact[7] = {720, 120, 24, 6, 2, 1, 1};
+    uint32_t code = 0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        uint32_t l = 0;
+#pragma unroll
+        for (int j = i + 1; j < 7; ++j) l += v[j] < v[i] ? 1u : 0u;
+        code += l * fact[i];
+    }
+    return side * kPerm7 + code;
+}
+
 template <int GX, int GY>
 struct Tile {
-    static_assert(GX * GY == kThreads, "one vertex per thread");
+    static_assert(GX * GY == kTileVerts, "tile holds kTileVerts vertices");
     static constexpr int HX = GX + 2, HY = GY + 2, HZ = 3;
     static constexpr int kHalo = HX * HY * HZ;
 };
@@ -247,7 +301,8 @@ __device__ __forceinline__ void gather_orders(const int32_t *tile, int c, int32_
 struct BlockShared {
     SharedTables T;
     uint32_t bins[kSizeBins];
-    uint16_t perm[kThreads];
+    uint16_t perm[kTileVerts];
+    uint8_t key[kTileVerts];
 };
 
 __device__ __forceinline__ void load_tables(SharedTables &T)
@@ -257,43 +312,59 @@ __device__ __forceinline__ void load_tables(SharedTables &T)
     for (int i = threadIdx.x; i < (int)(sizeof(SharedTables) / 4); i += kThreads) dst[i] = src[i];
 }
 
-// One GX x GY x 1 tile of the owned box [lo, lo + w) of a grid of dims n.
-// Stages the orders of the tile plus a one-vertex halo, then assigns the
-// tile's vertices to threads sorted by the size of their lower stars, so that
-// the vertices of a wave need similar numbers of steps (a wave runs as long as
-// its slowest lane).  Must be entered by the whole block.
+// One GX x GY x 1 tile (1024 vertices) of the owned box [lo, lo + w) of a
+// grid of dims n.  The orders of the tile plus a one-vertex halo are staged
+// in LDS.  Pass 1 visits the tile in order (4 vertices per thread): a vertex
+// whose lower neighbours are one of each opposite pair takes its record from
+// the precomputed table; any other vertex is binned by the size of its lower
+// star.  Pass 2 deals those vertices to threads by increasing size, so that
+// the vertices of a wave need similar numbers of steps (a wave runs as long
+// as its slowest lane).  Must be entered by the whole block.
 template <int GX, int GY>
-__device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order, int64_t nx, int64_t ny, int64_t nz,
-                              int64_t lo0, int64_t lo1, int64_t lo2, int64_t w0, int64_t w1,
-                              int64_t w2, int64_t bx, int64_t by, int64_t bz,
-                              uint4 *__restrict__ rec, BlockShared &sh, int32_t *tile)
+__device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order, int64_t nx,
+                                              int64_t ny, int64_t nz, int64_t lo0, int64_t lo1,
+                                              int64_t lo2, int64_t w0, int64_t w1, int64_t w2,
+                                              int64_t bx, int64_t by, int64_t bz,
+                                              uint4 *__restrict__ rec, BlockShared &sh, int32_t *tile)
 {
     using S = Tile<GX, GY>;
     const int tid = threadIdx.x;
     for (int i = tid; i < kSizeBins; i += kThreads) sh.bins[i] = 0;
     const int64_t x0 = lo0 + bx * GX - 1, y0 = lo1 + by * GY - 1, z0 = lo2 + bz - 1;
+    const bool full = x0 >= 0 && y0 >= 0 && z0 >= 0 && x0 + S::HX <= nx && y0 + S::HY <= ny &&
+                      z0 + S::HZ <= nz;
     for (int i = tid; i < S::kHalo; i += kThreads) {
         const int hx = i % S::HX, hy = (i / S::HX) % S::HY, hz = i / (S::HX * S::HY);
         const int64_t x = x0 + hx, y = y0 + hy, z = z0 + hz;
         int32_t v = kAbsent;
-        if (x >= 0 && y >= 0 && z >= 0 && x < nx && y < ny && z < nz) v = order[x + nx * (y + ny * z)];
+        if (full || (x >= 0 && y >= 0 && z >= 0 && x < nx && y < ny && z < nz))
+            v = order[x + nx * (y + ny * z)];
         tile[i] = v;
     }
     __syncthreads();
 
-    // lower-star size of the vertex at tile slot tid (0 outside the box)
-    int size = 0;
-    {
-        const int tx = tid % GX, ty = tid / GX;
+    // pass 1: regular vertices from the table; others get a size key
+    const int64_t rbase = (bx * GX) + w0 * ((by * GY) + w1 * bz);
+#pragma unroll
+    for (int k = 0; k < kTileVerts / kThreads; ++k) {
+        const int v = tid + k * kThreads;
+        const int tx = v % GX, ty = v / GX;
+        uint32_t key = kSizeBins;  // outside the box: no work
         if (bx * GX + tx < w0 && by * GY + ty < w1 && bz < w2) {
             const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
             int32_t o[14];
             gather_orders<GX, GY>(tile, c, o);
             const uint32_t low = lower_mask(o, tile[c]);
-            size = 1 + __popc(low) + __popcll(lower_star_tq(low));
+            uint32_t side;
+            if (regular_pattern(low, side)) {
+                rec[rbase + tx + w0 * ty] = g_regular[regular_index(o, side)];
+            } else {
+                key = 1 + __popc(low) + __popcll(lower_star_tq(low));
+                atomicAdd(&sh.bins[key], 1u);
+            }
         }
+        sh.key[v] = (uint8_t)(key < kSizeBins ? key : 0xffu);
     }
-    const uint32_t slot = atomicAdd(&sh.bins[size], 1u);
     __syncthreads();
     if (tid < kWave) {  // exclusive scan of the bins by the first wave
         const uint32_t v0 = tid < kSizeBins ? sh.bins[tid] : 0u;
@@ -309,25 +380,36 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
         if (tid + kWave < kSizeBins) sh.bins[tid + kWave] = tot0 + i1 - v1;
     }
     __syncthreads();
-    sh.perm[sh.bins[size] + slot] = (uint16_t)tid;
-    __syncthreads();
-
-    const int v = sh.perm[tid];
-    const int tx = v % GX, ty = v / GX;
-    const int64_t ox_ = bx * GX + tx, oy_ = by * GY + ty, oz_ = bz;  // box coordinates
-    const bool inside = ox_ < w0 && oy_ < w1 && oz_ < w2;
-    const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
-    int32_t o[14];
-    gather_orders<GX, GY>(tile, c, o);
-    const int m = inside ? __popc(lower_mask(o, tile[c])) : 0;
-    int mmax = m;
+    // deal the irregular vertices into perm by key (within a key any order)
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
-    mmax = __builtin_amdgcn_readfirstlane(mmax);
-    if (inside) {
-        uint4 r;
-        process_vertex(o, tile[c], mmax, sh.T, r);
-        rec[ox_ + w0 * (oy_ + w1 * oz_)] = r;
+    for (int k = 0; k < kTileVerts / kThreads; ++k) {
+        const int v = tid + k * kThreads;
+        const uint32_t key = sh.key[v];
+        if (key != 0xffu) sh.perm[atomicAdd(&sh.bins[key], 1u)] = (uint16_t)v;
+    }
+    __syncthreads();
+    // the last bin is never used (keys are at most 75): its start is the total
+    const uint32_t total = sh.bins[kSizeBins - 1];
+
+    // pass 2: irregular vertices by increasing lower-star size
+    for (uint32_t base = 0; base < total; base += kThreads) {
+        const uint32_t i = base + tid;
+        const bool active = i < total;
+        const int v = active ? sh.perm[i] : 0;
+        const int tx = v % GX, ty = v / GX;
+        const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
+        int32_t o[14];
+        gather_orders<GX, GY>(tile, c, o);
+        const int m = active ? __popc(lower_mask(o, tile[c])) : 0;
+        int mmax = m;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
+        mmax = __builtin_amdgcn_readfirstlane(mmax);
+        if (active) {
+            uint4 r;
+            process_vertex(o, tile[c], mmax, sh.T, r);
+            rec[rbase + tx + w0 * ty] = r;
+        }
     }
 }
 
@@ -350,10 +432,10 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict
 // Batched form: many whole fields, concatenated; a persistent grid walks the
 // (field, tile) list, field f owning tiles [tile_start[f], tile_start[f+1]).
 template <int GX, int GY>
-__global__ __launch_bounds__(kThreads) void k_gradient_batch(const int32_t *__restrict__ order,
-                                                             const BatchField *__restrict__ fields,
-                                                             int nfields, const int64_t *tile_start,
-                                                             uint4 *__restrict__ rec)
+__global__ __launch_bounds__(kThreads, 5) void k_gradient_batch(const int32_t *__restrict__ order,
+                                                                const BatchField *__restrict__ fields,
+                                                                int nfields, const int64_t *tile_start,
+                                                                uint4 *__restrict__ rec)
 {
     __shared__ BlockShared sh;
     __shared__ int32_t tile[Tile<GX, GY>::kHalo];
@@ -368,6 +450,7 @@ __global__ __launch_bounds__(kThreads) void k_gradient_batch(const int32_t *__re
             const int mid = (lo + hi + 1) >> 1;
             if (tstart[mid] <= t) lo = mid; else hi = mid - 1;
         }
+        lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: the block's field
         const BatchField F = fields[lo];
         const int64_t bxc = (F.n[0] + GX - 1) / GX, byc = (F.n[1] + GY - 1) / GY;
         const int64_t k = t - tstart[lo];
@@ -378,22 +461,77 @@ __global__ __launch_bounds__(kThreads) void k_gradient_batch(const int32_t *__re
     }
 }
 
+// Fills the regular-vertex table: entry side * 5040 + code holds the record of
+// the configuration whose lower neighbours are, for pair i, neighbour i or
+// 13 - i (bit i of side), ordered by the permutation with Lehmer code `code`.
+__global__ __launch_bounds__(kThreads) void k_regular_table()
+{
+    __shared__ SharedTables T;
+    load_tables(T);
+    __syncthreads();
+    const int idx = blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= kRegular) return;
+    const uint32_t side = idx / kPerm7;
+    uint32_t code = idx % kPerm7;
+    // decode the Lehmer code into the ranks of the 7 lower neighbours
+    const uint32_t fact[7] = {720, 120, 24, 6, 2, 1, 1};
+    uint32_t used = 0, rank[7];
+    for (int i = 0; i < 7; ++i) {
+        uint32_t l = code / fact[i];
+        code %= fact[i];
+        // the l-th smallest unused rank
+        int r = 0;
+        for (;; ++r)
+            if (!((used >> r) & 1u)) {
+                if (l == 0) break;
+                --l;
+            }
+        used |= 1u << r;
+        rank[i] = (uint32_t)r;
+    }
+    int32_t o[14];
+    for (int i = 0; i < 7; ++i) {
+        const int lowm = ((side >> i) & 1u) ? 13 - i : i;
+        o[lowm] = (int32_t)rank[i];
+        o[13 - lowm] = 100 + i;  // above x
+    }
+    uint4 r;
+    process_vertex(o, 50, 14, T, r);
+    g_regular[idx] = r;
+}
+
 }  // namespace
 }  // namespace dms
 
 namespace dms {
+
+namespace {
+std::atomic<uint64_t> g_regular_ready{0};  // one bit per device that holds the table
+}
+
+int ensure_regular_table(hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DMS_E_HIP;
+    const uint64_t bit = 1ull << dev;
+    if (g_regular_ready.load() & bit) return DMS_OK;
+    hipLaunchKernelGGL(k_regular_table, dim3((kRegular + kThreads - 1) / kThreads), dim3(kThreads), 0, s);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return DMS_E_HIP;
+    g_regular_ready.fetch_or(bit);
+    return DMS_OK;
+}
 
 int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
                     const int64_t *hi, uint32_t *rec, hipStream_t s)
 {
     const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
     if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
-    const int gx = kTileX[variant], gy = kThreads / gx;
+    const int gx = kTileX[variant], gy = kTileVerts / gx;
     const int64_t bxc = (w0 + gx - 1) / gx, byc = (w1 + gy - 1) / gy;
     const int64_t blocks = bxc * byc * w2;
     if (blocks > 2147483647LL) return DMS_E_SIZE;
 #define DMS_LAUNCH(GXV)                                                                              \
-    hipLaunchKernelGGL((k_gradient<GXV, kThreads / GXV>), dim3((unsigned)blocks), dim3(kThreads), 0, s, \
+    hipLaunchKernelGGL((k_gradient<GXV, kTileVerts / GXV>), dim3((unsigned)blocks), dim3(kThreads), 0, s, \
                        order, dims[0], dims[1], dims[2], lo[0], lo[1], lo[2], w0, w1, w2, bxc, byc,  \
                        (uint4 *)rec)
     switch (variant) {
@@ -412,7 +550,7 @@ int launch_gradient_batch(int variant, const int32_t *order, const BatchField *f
     if (total_tiles == 0) return DMS_OK;
     const unsigned g = (unsigned)(total_tiles < grid ? total_tiles : grid);
 #define DMS_LAUNCH(GXV)                                                                          \
-    hipLaunchKernelGGL((k_gradient_batch<GXV, kThreads / GXV>), dim3(g), dim3(kThreads), 0, s,  \
+    hipLaunchKernelGGL((k_gradient_batch<GXV, kTileVerts / GXV>), dim3(g), dim3(kThreads), 0, s,  \
                        order, fields, nfields, tile_start, (uint4 *)rec)
     switch (variant) {
     case 0: DMS_LAUNCH(64); break;
@@ -430,9 +568,9 @@ int gradient_batch_grid(int variant)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     hipError_t e;
     switch (variant) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<64, 4>, kThreads, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<32, 8>, kThreads, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<16, 16>, kThreads, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<64, 16>, kThreads, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<32, 32>, kThreads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<16, 64>, kThreads, 0); break;
     }
     if (e != hipSuccess || per < 1) per = 1;
     return cus * per;
@@ -449,5 +587,7 @@ extern "C" int dms_discrete_gradient(const int32_t *order, const int64_t dims[3]
     const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
     if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
     if (!order || !rec) return DMS_E_ARG;
+    const int st = ensure_regular_table((hipStream_t)stream);
+    if (st) return st;
     return launch_gradient(0, order, dims, lo, hi, rec, (hipStream_t)stream);
 }

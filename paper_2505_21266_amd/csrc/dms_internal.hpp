@@ -15,10 +15,13 @@ struct BatchField {
     int64_t off;
 };
 
-// Gradient tile shapes (x extent; 256 threads per tile): 64x4, 32x8, 16x16.
+// Gradient tile shapes (x extent; 1024 vertices per tile): 64x16, 32x32, 16x64.
+constexpr int kTileVertsPerBlock = 1024;
 constexpr int kGradVariants = 3;
 constexpr int kTileX[kGradVariants] = {64, 32, 16};
 
+// Fills the device's regular-vertex table on first use (one synchronisation).
+int ensure_regular_table(hipStream_t s);
 int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
                     const int64_t *hi, uint32_t *rec, hipStream_t s);
 int gradient_batch_grid(int variant);  // persistent grid size (CUs x resident blocks)
