@@ -18,6 +18,8 @@ namespace dms {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kPerThread = 4;
+constexpr int kTileRecs = kThreads * kPerThread;  // records per block
 
 struct Fields {
     uint64_t lo, hi;
@@ -31,13 +33,18 @@ __device__ __forceinline__ uint32_t tri_field(uint64_t lo, uint64_t hi, int t)
     return (uint32_t)((b < 64 ? lo >> b : hi >> (b - 64)) & 3u);
 }
 
-// L(x) edge mask from the edge fields
+// L(x) edge mask from the edge fields: bit e set iff edge field e is non-zero
+// (nibble-wise OR, then the 14 nibble bits compressed into 14 adjacent bits)
 __device__ __forceinline__ uint32_t lower_edges(uint64_t lo)
 {
-    uint32_t low = 0;
-#pragma unroll
-    for (int e = 0; e < 14; ++e) low |= (edge_field(lo, e) != 0 ? 1u : 0u) << e;
-    return low;
+    uint64_t x = lo | (lo >> 1);
+    x |= x >> 2;
+    x &= 0x0011111111111111ull;                   // bit 4e
+    x = (x | (x >> 3)) & 0x0003030303030303ull;   // bits 8j, 8j+1
+    x = (x | (x >> 6)) & 0x000f000f000f000full;   // nibbles at 16j
+    x = (x | (x >> 12)) & 0x000000ff000000ffull;  // bytes at 32j
+    x = (x | (x >> 24)) & 0xffffull;
+    return (uint32_t)x;
 }
 
 __device__ __forceinline__ uint64_t lower_tris(uint32_t low)
@@ -146,23 +153,71 @@ __device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint
     }
 }
 
+// Per-record counts packed in 16-bit lanes (dimension d in bits 16d..16d+15);
+// a block's sums fit: at most 36 x 1024 cells of one dimension.
+__device__ __forceinline__ uint64_t pack4(const uint32_t *c)
+{
+    return (uint64_t)c[0] | ((uint64_t)c[1] << 16) | ((uint64_t)c[2] << 32) | ((uint64_t)c[3] << 48);
+}
+
+__device__ __forceinline__ uint32_t lane16(uint64_t v, int d) { return (uint32_t)(v >> (16 * d)) & 0xffffu; }
+
+__device__ __forceinline__ void load_recs(const uint4 *__restrict__ rec, int64_t nbox, int64_t r0,
+                                          uint64_t *lo, uint64_t *hi, uint64_t *packed)
+{
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        uint32_t c[4] = {0, 0, 0, 0};
+        lo[k] = hi[k] = 0;
+        if (r0 + k < nbox) {
+            const uint4 w = rec[r0 + k];
+            lo[k] = (uint64_t)w.x | ((uint64_t)w.y << 32);
+            hi[k] = (uint64_t)w.z | ((uint64_t)w.w << 32);
+            count_critical(lo[k], hi[k], c);
+        }
+        packed[k] = pack4(c);
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec, int64_t nbox,
                                                          uint64_t *__restrict__ tile_counts,
                                                          int64_t ntiles)
 {
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    uint32_t c[4] = {0, 0, 0, 0};
-    if (r < nbox) {
-        const uint4 w = rec[r];
-        count_critical((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), c);
-    }
+    __shared__ uint64_t wsum[kThreads / kWave];
+    const int64_t r0 = (int64_t)blockIdx.x * kTileRecs + (int64_t)threadIdx.x * kPerThread;
+    uint64_t lo[kPerThread], hi[kPerThread], pk[kPerThread];
+    load_recs(rec, nbox, r0, lo, hi, pk);
+    uint64_t sum = pk[0] + pk[1] + pk[2] + pk[3];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        uint64_t total;
-        block_exclusive_scan<uint64_t>(c[d], &total);
-        if (threadIdx.x == 0) tile_counts[(int64_t)d * ntiles + blockIdx.x] = total;
+    for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if (lane_id() == 0) wsum[threadIdx.x / kWave] = sum;
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / kWave; ++w) t += wsum[w];
+        tile_counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = lane16(t, threadIdx.x);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) tile_counts[4 * ntiles] = 0;
+}
+
+// Shared by the single-field and batched fill: records [r0, r0 + 4) of
+// this thread, their packed counts, and the first slot of each list for
+// the first of them.
+__device__ __forceinline__ void fill_slots(const uint64_t *pk, const uint64_t *__restrict__ offs,
+                                           int64_t ntiles, uint64_t at[kPerThread][4])
+{
+    uint64_t total;
+    uint64_t run = block_exclusive_scan<uint64_t>(pk[0] + pk[1] + pk[2] + pk[3], &total);
+    uint64_t base[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) base[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) at[k][d] = base[d] + lane16(run, d);
+        run += pk[k];
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_crit_fill(
@@ -171,25 +226,19 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill(
     int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
     int64_t cap2, int64_t cap3)
 {
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    uint32_t c[4] = {0, 0, 0, 0};
-    uint64_t lo = 0, hi = 0;
-    if (r < nbox) {
-        const uint4 w = rec[r];
-        lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
-        hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
-        count_critical(lo, hi, c);
-    }
-    uint64_t at[4];
+    const int64_t r0 = (int64_t)blockIdx.x * kTileRecs + (int64_t)threadIdx.x * kPerThread;
+    uint64_t lo[kPerThread], hi[kPerThread], pk[kPerThread], at[kPerThread][4];
+    load_recs(rec, nbox, r0, lo, hi, pk);
+    fill_slots(pk, offs, ntiles, at);
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        uint64_t total;
-        const uint64_t ex = block_exclusive_scan<uint64_t>(c[d], &total);
-        at[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles] + ex;
+    for (int k = 0; k < kPerThread; ++k) {
+        if (r0 + k >= nbox || pk[k] == 0) continue;
+        uint32_t c[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
+        const int64_t v = box_vertex(r0 + k, w0, w1, lo0, lo1, lo2, nx, ny);
+        write_codes(lo[k], hi[k], c, at[k], v << 8, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
     }
-    if (r >= nbox || (c[0] | c[1] | c[2] | c[3]) == 0) return;
-    const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
-    write_codes(lo, hi, c, at, v << 8, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 }
 
 __global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *counts, int64_t cap0,
@@ -217,33 +266,28 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
 {
     __shared__ int64_t so[kMaxBatchFields + 1];
     for (int i = threadIdx.x; i <= nfields; i += kThreads) so[i] = foff[i];
-    __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    uint32_t c[4] = {0, 0, 0, 0};
-    uint64_t lo = 0, hi = 0;
-    if (r < nbox) {
-        const uint4 w = rec[r];
-        lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
-        hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
-        count_critical(lo, hi, c);
-    }
-    uint64_t at[4];
+    const int64_t r0 = (int64_t)blockIdx.x * kTileRecs + (int64_t)threadIdx.x * kPerThread;
+    uint64_t lo[kPerThread], hi[kPerThread], pk[kPerThread], at[kPerThread][4];
+    load_recs(rec, nbox, r0, lo, hi, pk);
+    fill_slots(pk, offs, ntiles, at);  // its barriers also publish so[]
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        uint64_t total;
-        const uint64_t ex = block_exclusive_scan<uint64_t>(c[d], &total);
-        at[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles] + ex;
+    for (int k = 0; k < kPerThread; ++k) {
+        const int64_t r = r0 + k;
+        if (r >= nbox) continue;
+        int f0 = 0, f1 = nfields - 1;
+        while (f0 < f1) {
+            const int mid = (f0 + f1 + 1) >> 1;
+            if (so[mid] <= r) f0 = mid; else f1 = mid - 1;
+        }
+        if (r == so[f0])
+            for (int d = 0; d < 4; ++d) fstart[(int64_t)d * (nfields + 1) + f0] = (int64_t)at[k][d];
+        if (pk[k] == 0) continue;
+        uint32_t c[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
+        write_codes(lo[k], hi[k], c, at[k], (r - so[f0]) << 8, crit0, crit1, crit2, crit3, cap0, cap1,
+                    cap2, cap3);
     }
-    if (r >= nbox) return;
-    int f0 = 0, f1 = nfields - 1;
-    while (f0 < f1) {
-        const int mid = (f0 + f1 + 1) >> 1;
-        if (so[mid] <= r) f0 = mid; else f1 = mid - 1;
-    }
-    if (r == so[f0])
-        for (int d = 0; d < 4; ++d) fstart[(int64_t)d * (nfields + 1) + f0] = (int64_t)at[d];
-    if ((c[0] | c[1] | c[2] | c[3]) == 0) return;
-    write_codes(lo, hi, c, at, (r - so[f0]) << 8, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 }
 
 __global__ void k_crit_finish_batch(const uint64_t *offs, int64_t ntiles, int nfields, int64_t *fstart,
@@ -280,7 +324,7 @@ namespace dms {
 size_t critical_batch_workspace_size(int64_t n, int nfields)
 {
     (void)nfields;
-    const int64_t ntiles = (n + kThreads - 1) / kThreads;
+    const int64_t ntiles = (n + kTileRecs - 1) / kTileRecs;
     const int64_t len = 4 * ntiles + 1;
     return align_up((size_t)len * 8, 256) + scan_partials_bytes(len, 8);
 }
@@ -291,7 +335,7 @@ int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, i
                           hipStream_t s)
 {
     (void)fields;
-    const int64_t ntiles = (n + kThreads - 1) / kThreads;
+    const int64_t ntiles = (n + kTileRecs - 1) / kTileRecs;
     const int64_t len = 4 * ntiles + 1;
     uint64_t *tc = (uint64_t *)ws;
     uint64_t *partials = (uint64_t *)(ws + align_up((size_t)len * 8, 256));
@@ -314,7 +358,7 @@ extern "C" size_t dms_critical_workspace_size(const int64_t dims[3], const int64
     using namespace dms;
     if (!box_valid(dims, lo, hi)) return 0;
     const int64_t nbox = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
-    const int64_t ntiles = (nbox + kThreads - 1) / kThreads;
+    const int64_t ntiles = (nbox + kTileRecs - 1) / kTileRecs;
     const int64_t len = 4 * ntiles + 1;
     return align_up((size_t)len * 8, 256) + scan_partials_bytes(len, 8);
 }
@@ -338,7 +382,7 @@ extern "C" int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3]
     const size_t need = dms_critical_workspace_size(dims, lo, hi);
     if (!workspace || workspace_bytes < need) return DMS_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    const int64_t ntiles = (nbox + kThreads - 1) / kThreads;
+    const int64_t ntiles = (nbox + kTileRecs - 1) / kTileRecs;
     const int64_t len = 4 * ntiles + 1;
     uint64_t *tc = (uint64_t *)workspace;
     uint64_t *partials = (uint64_t *)((char *)workspace + align_up((size_t)len * 8, 256));
