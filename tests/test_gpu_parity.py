@@ -86,6 +86,47 @@ def test_order_nan_flag(dtype):
         dms.order(_dev(v))
 
 
+def _check_order_gpu(v, o):
+    """o is the order of v iff it is a permutation of [0, n) whose inverse
+    lists v in (value, id) order: that order is unique."""
+    n = v.numel()
+    o = o.reshape(-1)
+    assert int(o.min()) >= 0 and int(o.max()) < n
+    inv = torch.full((n,), -1, dtype=torch.int64, device=v.device)
+    inv[o.long()] = torch.arange(n, device=v.device)
+    assert bool((inv >= 0).all())
+    vs = v.reshape(-1)[inv]
+    assert bool((vs[1:] >= vs[:-1]).all())
+    ties = vs[1:] == vs[:-1]
+    assert bool((inv[1:][ties] > inv[:-1][ties]).all())
+
+
+# sizes past 2^22 take the two-level inversion (coarse id buckets, then a
+# fine partition inside each), the rest the one-level one
+@pytest.mark.parametrize("n,kind,dtype", [(4194305, "noise", np.float32),
+                                          (16777216, "ties", np.float32),
+                                          (33554467, "noise", np.float32),
+                                          (4194305, "ties", np.float64)])
+def test_order_two_level_inversion(n, kind, dtype):
+    rng = np.random.default_rng(n + 5)
+    v = rng.random(n).astype(dtype) if kind == "noise" else rng.integers(0, 1000, n).astype(dtype)
+    _say("order two-level", n, kind, np.dtype(dtype).name)
+    got = dms.order(_dev(v))
+    assert (got.cpu().numpy() == oracle.order(v)).all()
+
+
+def test_order_full_block():
+    """The 1026^3 float32 block of 512 Gaussians plus noise (over 2^30
+    vertices, so the widest inversion window), checked by the properties that
+    fix the order uniquely."""
+    v, _, _ = inputs.config3()
+    _say("order full block", v.shape)
+    vt = _dev(v)
+    del v
+    o = dms.order(vt)
+    _check_order_gpu(vt, o)
+
+
 def test_order_config1():
     v = inputs.config1()
     got = dms.order(_dev(v)).cpu().numpy()
