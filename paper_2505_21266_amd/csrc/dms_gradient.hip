@@ -17,6 +17,7 @@
 // enter the one-facet queue; entries of the zero queue that get paired are
 // dropped (Robins' lazy deletion gives the same pops).
 #include <atomic>
+#include <mutex>
 
 #include "dms_common.hpp"
 #include "dms_internal.hpp"
@@ -282,6 +283,69 @@ __device__ __forceinline__ uint32_t regular_index(const int32_t *o, uint32_t sid
     return side * kPerm7 + code;
 }
 
+// One-defect vertices: six pairs have one lower member and the seventh has
+// both (8 lower neighbours) or neither (6).  The records of these two
+// families are tabulated the same way, by defect pair j, the sides of the
+// other six pairs and the order of the lower neighbours:
+//   |L| = 8: index ((j * 64 + side6) * 8! + code8) -- 289 MB, allocated once
+//            per device; the order is that of v[i] = lower member of pair i
+//            (neighbour 13 - i for i = j) for i < 7, then v[7] = neighbour j;
+//   |L| = 6: index ((j * 64 + side6) * 6! + code6), the order of the lower
+//            members of the pairs other than j, in pair order.
+// side6 is the 7-bit side pattern with bit j removed.
+constexpr int kPerm6 = 720;
+constexpr int kPerm8 = 40320;
+constexpr int kDefect6 = 7 * 64 * kPerm6;
+constexpr int64_t kDefect8 = 7ll * 64 * kPerm8;
+__device__ uint4 g_defect6[kDefect6];
+
+// Record of x from one of the tables, or null when x is in none of the
+// families (defect8 may be null: that family then takes the general path).
+__device__ __forceinline__ const uint4 *table_entry(uint32_t low, const int32_t *o,
+                                                    const uint4 *__restrict__ defect8)
+{
+    uint32_t side;
+    if (regular_pattern(low, side)) return &g_regular[regular_index(o, side)];
+    const uint32_t rev = __brev(low) >> 18;
+    const uint32_t one = (low ^ rev) & 0x7fu;
+    if (__popc(one) != 6) return nullptr;
+    const uint32_t j = (uint32_t)__ffs(~one & 0x7fu) - 1u;
+    const uint32_t side6 = (side & ((1u << j) - 1u)) | ((side >> (j + 1u)) << j);
+    int32_t v[8];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) v[i] = ((side >> i) & 1u) ? o[13 - i] : o[i];
+    if ((low >> j) & 1u) {  // pair j wholly lower
+        if (!defect8) return nullptr;
+        int32_t oj = 0;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) oj = (uint32_t)i == j ? o[i] : oj;
+        v[7] = oj;
+        uint32_t code = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            uint32_t l = 0;
+#pragma unroll
+            for (int k = i + 1; k < 8; ++k) l += v[k] < v[i] ? 1u : 0u;
+            code = code * (uint32_t)(8 - i) + l;
+        }
+        return defect8 + ((int64_t)(j * 64u + side6) * kPerm8 + code);
+    }
+    // pair j wholly upper: skip its slot (a sentinel above every order keeps
+    // it out of the other slots' counts)
+#pragma unroll
+    for (int i = 0; i < 7; ++i) v[i] = (uint32_t)i == j ? 0x7fffffff : v[i];
+    uint32_t code = 0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        uint32_t l = 0;
+#pragma unroll
+        for (int k = i + 1; k < 7; ++k) l += v[k] < v[i] ? 1u : 0u;
+        const uint32_t left = (uint32_t)i > j ? 7u - i : 6u - i;  // slots still to come
+        code = (uint32_t)i == j ? code : code * left + l;
+    }
+    return &g_defect6[(j * 64u + side6) * kPerm6 + code];
+}
+
 template <int GX, int GY>
 struct Tile {
     static_assert(GX * GY == kTileVerts, "tile holds kTileVerts vertices");
@@ -314,10 +378,9 @@ __device__ __forceinline__ void load_tables(SharedTables &T)
 
 // One GX x GY x 1 tile (1024 vertices) of the owned box [lo, lo + w) of a
 // grid of dims n.  The orders of the tile plus a one-vertex halo are staged
-// in LDS.  Pass 1 visits the tile in order (4 vertices per thread): a vertex
-// whose lower neighbours are one of each opposite pair takes its record from
-// the precomputed table; any other vertex is binned by the size of its lower
-// star.  Pass 2 deals those vertices to threads by increasing size, so that
+// in LDS.  Pass 1 visits the tile in order (4 vertices per thread): a
+// regular or one-defect vertex takes its record from the precomputed
+// tables; any other vertex is binned by the size of its lower star.  Pass 2 deals those vertices to threads by increasing size, so that
 // the vertices of a wave need similar numbers of steps (a wave runs as long
 // as its slowest lane).  Must be entered by the whole block.
 template <int GX, int GY>
@@ -325,7 +388,8 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
                                               int64_t ny, int64_t nz, int64_t lo0, int64_t lo1,
                                               int64_t lo2, int64_t w0, int64_t w1, int64_t w2,
                                               int64_t bx, int64_t by, int64_t bz,
-                                              uint4 *__restrict__ rec, BlockShared &sh, int32_t *tile)
+                                              uint4 *__restrict__ rec, const uint4 *__restrict__ defect8,
+                                              BlockShared &sh, int32_t *tile)
 {
     using S = Tile<GX, GY>;
     const int tid = threadIdx.x;
@@ -355,9 +419,9 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
             int32_t o[14];
             gather_orders<GX, GY>(tile, c, o);
             const uint32_t low = lower_mask(o, tile[c]);
-            uint32_t side;
-            if (regular_pattern(low, side)) {
-                rec[rbase + tx + w0 * ty] = g_regular[regular_index(o, side)];
+            const uint4 *hit = table_entry(low, o, defect8);
+            if (hit) {
+                rec[rbase + tx + w0 * ty] = *hit;
             } else {
                 key = 1 + __popc(low) + __popcll(lower_star_tq(low));
                 atomicAdd(&sh.bins[key], 1u);
@@ -419,14 +483,16 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict
                                                        int64_t lo0, int64_t lo1, int64_t lo2,
                                                        int64_t w0, int64_t w1, int64_t w2,
                                                        int64_t bx_count, int64_t by_count,
-                                                       uint4 *__restrict__ rec)
+                                                       uint4 *__restrict__ rec,
+                                                       const uint4 *__restrict__ defect8)
 {
     __shared__ BlockShared sh;
     __shared__ int32_t tile[Tile<GX, GY>::kHalo];
     load_tables(sh.T);
     const int64_t b = blockIdx.x;
     const int64_t bx = b % bx_count, by = (b / bx_count) % by_count, bz = b / (bx_count * by_count);
-    gradient_tile<GX, GY>(order, nx, ny, nz, lo0, lo1, lo2, w0, w1, w2, bx, by, bz, rec, sh, tile);
+    gradient_tile<GX, GY>(order, nx, ny, nz, lo0, lo1, lo2, w0, w1, w2, bx, by, bz, rec, defect8, sh,
+                          tile);
 }
 
 // Batched form: many whole fields, concatenated; a persistent grid walks the
@@ -435,7 +501,8 @@ template <int GX, int GY>
 __global__ __launch_bounds__(kThreads, 5) void k_gradient_batch(const int32_t *__restrict__ order,
                                                                 const BatchField *__restrict__ fields,
                                                                 int nfields, const int64_t *tile_start,
-                                                                uint4 *__restrict__ rec)
+                                                                uint4 *__restrict__ rec,
+                                                                const uint4 *__restrict__ defect8)
 {
     __shared__ BlockShared sh;
     __shared__ int32_t tile[Tile<GX, GY>::kHalo];
@@ -456,8 +523,31 @@ __global__ __launch_bounds__(kThreads, 5) void k_gradient_batch(const int32_t *_
         const int64_t k = t - tstart[lo];
         const int64_t bx = k % bxc, by = (k / bxc) % byc, bz = k / (bxc * byc);
         gradient_tile<GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1], F.n[2],
-                              bx, by, bz, rec + F.off, sh, tile);
+                              bx, by, bz, rec + F.off, defect8, sh, tile);
         __syncthreads();  // the next tile reuses the shared buffers
+    }
+}
+
+// Decodes a Lehmer code (factorial base, first item most significant) of
+// N items into their ranks.
+template <int N>
+__device__ void lehmer_decode(uint32_t code, uint32_t *rank)
+{
+    uint32_t w = 1;
+    for (int i = 2; i < N; ++i) w *= (uint32_t)i;  // (N - 1)!
+    uint32_t used = 0;
+    for (int i = 0; i < N; ++i) {
+        uint32_t l = code / w;
+        code %= w;
+        if (i < N - 1) w /= (uint32_t)(N - 1 - i);
+        int r = 0;  // the l-th smallest unused rank
+        for (;; ++r)
+            if (!((used >> r) & 1u)) {
+                if (l == 0) break;
+                --l;
+            }
+        used |= 1u << r;
+        rank[i] = (uint32_t)r;
     }
 }
 
@@ -472,23 +562,8 @@ __global__ __launch_bounds__(kThreads) void k_regular_table()
     const int idx = blockIdx.x * kThreads + threadIdx.x;
     if (idx >= kRegular) return;
     const uint32_t side = idx / kPerm7;
-    uint32_t code = idx % kPerm7;
-    // decode the Lehmer code into the ranks of the 7 lower neighbours
-    const uint32_t fact[7] = {720, 120, 24, 6, 2, 1, 1};
-    uint32_t used = 0, rank[7];
-    for (int i = 0; i < 7; ++i) {
-        uint32_t l = code / fact[i];
-        code %= fact[i];
-        // the l-th smallest unused rank
-        int r = 0;
-        for (;; ++r)
-            if (!((used >> r) & 1u)) {
-                if (l == 0) break;
-                --l;
-            }
-        used |= 1u << r;
-        rank[i] = (uint32_t)r;
-    }
+    uint32_t rank[7];
+    lehmer_decode<7>(idx % kPerm7, rank);
     int32_t o[14];
     for (int i = 0; i < 7; ++i) {
         const int lowm = ((side >> i) & 1u) ? 13 - i : i;
@@ -500,13 +575,48 @@ __global__ __launch_bounds__(kThreads) void k_regular_table()
     g_regular[idx] = r;
 }
 
+// Fills a one-defect table (8 lower neighbours when eight, else 6), in the
+// layout table_entry reads.
+template <bool kEight>
+__global__ __launch_bounds__(kThreads) void k_defect_table(uint4 *table)
+{
+    __shared__ SharedTables T;
+    load_tables(T);
+    __syncthreads();
+    constexpr int N = kEight ? 8 : 6;
+    constexpr int64_t perms = kEight ? kPerm8 : kPerm6;
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (idx >= 7 * 64 * perms) return;
+    const uint32_t code = (uint32_t)(idx % perms);
+    const uint32_t js = (uint32_t)(idx / perms);
+    const uint32_t j = js / 64, side6 = js % 64;
+    // the 7-bit side pattern with bit j (pair j) set for both lower
+    const uint32_t side = (side6 & ((1u << j) - 1u)) | ((side6 >> j) << (j + 1u)) |
+                          (kEight ? 1u << j : 0u);
+    uint32_t rank[N];
+    lehmer_decode<N>(code, rank);
+    int32_t o[14];
+    for (int e = 0; e < 14; ++e) o[e] = 100 + e;  // above x unless set below
+    int p = 0;
+    for (int i = 0; i < 7; ++i) {
+        if (!kEight && (uint32_t)i == j) continue;
+        o[((side >> i) & 1u) ? 13 - i : i] = (int32_t)rank[p++];
+    }
+    if (kEight) o[j] = (int32_t)rank[7];
+    uint4 r;
+    process_vertex(o, 50, 14, T, r);
+    table[idx] = r;
+}
+
 }  // namespace
 }  // namespace dms
 
 namespace dms {
 
 namespace {
-std::atomic<uint64_t> g_regular_ready{0};  // one bit per device that holds the table
+std::atomic<uint64_t> g_regular_ready{0};  // one bit per device that holds the tables
+std::mutex g_table_mutex;
+uint4 *g_defect8_ptr[64];  // per device, held until the process ends
 }
 
 int ensure_regular_table(hipStream_t s)
@@ -515,10 +625,31 @@ int ensure_regular_table(hipStream_t s)
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DMS_E_HIP;
     const uint64_t bit = 1ull << dev;
     if (g_regular_ready.load() & bit) return DMS_OK;
+    std::lock_guard<std::mutex> lock(g_table_mutex);
+    if (g_regular_ready.load() & bit) return DMS_OK;
+    if (!g_defect8_ptr[dev]) {
+        void *p = nullptr;
+        if (hipMalloc(&p, (size_t)kDefect8 * sizeof(uint4)) != hipSuccess) return DMS_E_HIP;
+        g_defect8_ptr[dev] = (uint4 *)p;
+    }
+    uint4 *d6 = nullptr;
+    if (hipGetSymbolAddress((void **)&d6, HIP_SYMBOL(g_defect6)) != hipSuccess) return DMS_E_HIP;
     hipLaunchKernelGGL(k_regular_table, dim3((kRegular + kThreads - 1) / kThreads), dim3(kThreads), 0, s);
+    hipLaunchKernelGGL(k_defect_table<false>, dim3((kDefect6 + kThreads - 1) / kThreads), dim3(kThreads),
+                       0, s, d6);
+    hipLaunchKernelGGL(k_defect_table<true>, dim3((unsigned)((kDefect8 + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, g_defect8_ptr[dev]);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return DMS_E_HIP;
     g_regular_ready.fetch_or(bit);
     return DMS_OK;
+}
+
+// The current device's |L| = 8 table (null before ensure_regular_table).
+static const uint4 *defect8_table()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    return (g_regular_ready.load() >> dev) & 1u ? g_defect8_ptr[dev] : nullptr;
 }
 
 int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
@@ -530,10 +661,11 @@ int launch_gradient(int variant, const int32_t *order, const int64_t *dims, cons
     const int64_t bxc = (w0 + gx - 1) / gx, byc = (w1 + gy - 1) / gy;
     const int64_t blocks = bxc * byc * w2;
     if (blocks > 2147483647LL) return DMS_E_SIZE;
+    const uint4 *d8 = defect8_table();
 #define DMS_LAUNCH(GXV)                                                                              \
     hipLaunchKernelGGL((k_gradient<GXV, kTileVerts / GXV>), dim3((unsigned)blocks), dim3(kThreads), 0, s, \
                        order, dims[0], dims[1], dims[2], lo[0], lo[1], lo[2], w0, w1, w2, bxc, byc,  \
-                       (uint4 *)rec)
+                       (uint4 *)rec, d8)
     switch (variant) {
     case 0: DMS_LAUNCH(64); break;
     case 1: DMS_LAUNCH(32); break;
@@ -549,9 +681,10 @@ int launch_gradient_batch(int variant, const int32_t *order, const BatchField *f
 {
     if (total_tiles == 0) return DMS_OK;
     const unsigned g = (unsigned)(total_tiles < grid ? total_tiles : grid);
+    const uint4 *d8 = defect8_table();
 #define DMS_LAUNCH(GXV)                                                                          \
     hipLaunchKernelGGL((k_gradient_batch<GXV, kTileVerts / GXV>), dim3(g), dim3(kThreads), 0, s,  \
-                       order, fields, nfields, tile_start, (uint4 *)rec)
+                       order, fields, nfields, tile_start, (uint4 *)rec, d8)
     switch (variant) {
     case 0: DMS_LAUNCH(64); break;
     case 1: DMS_LAUNCH(32); break;

@@ -12,8 +12,9 @@
 // that the inversion's scattered writes stay inside a window of a few
 // buckets instead of covering the whole order array.
 //
-// Each pass: (1) per-tile digit histograms, (2) a device-wide exclusive scan
-// of the digit-major histogram matrix, (3) a stable per-tile scatter.  Tiles
+// Each pass: (1) per-tile digit histograms (LDS atomics), (2) a device-wide
+// exclusive scan of the digit-major histogram matrix, (3) a stable per-tile
+// scatter.  Tiles
 // hold 4096 keys (256 threads x 16 items, wave-striped so that a wave's items
 // are in element order); ranks inside a wave come from ballot-based digit
 // matching, ranks across waves from per-wave digit counts in LDS.
@@ -61,6 +62,22 @@ __device__ __forceinline__ int64_t elem_index(int64_t tile, int wave, int k, int
     return tile * kTile + (int64_t)wave * (kItems * kWave) + k * kWave + lane;
 }
 
+// Histogram update for one item per lane (counts only, no ranks): an LDS
+// atomic per lane, or a single add when the whole wave holds one digit, as
+// it does for the high key bytes of smooth fields.
+__device__ __forceinline__ void hist_add(uint32_t *h, uint32_t d, bool valid)
+{
+    const uint64_t act = __ballot(valid);
+    if (act == 0) return;
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(valid ? d : 0xffffffffu);
+    const uint64_t same = __ballot(valid && d == d0);
+    if (same == act) {
+        if (lane_id() == (int)__builtin_ctzll(act)) atomicAdd(&h[d0], (uint32_t)__popcll(act));
+    } else if (valid) {
+        atomicAdd(&h[d], 1u);
+    }
+}
+
 template <typename V, typename K, bool kFirst>
 __device__ __forceinline__ K load_key(const void *src, int64_t i, bool &nan)
 {
@@ -94,14 +111,14 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t
     bool nan_any = false;
     uint32_t dig[kItems];
     if (ids) {
+        uint32_t bk[kItems];
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const int64_t i = elem_index(tile, wave, k, lane);
-            const bool valid = i < n;
-            const uint32_t b = valid ? (ids[i] >> bshift) & (kRadix - 1) : 0u;
-            const uint64_t peers = match_digit8(b, __ballot(valid));
-            if (valid && (peers & lanemask_lt()) == 0) bhist[wave][b] += (uint32_t)__popcll(peers);
+            bk[k] = i < n ? (ids[i] >> bshift) & (kRadix - 1) : (uint32_t)kRadix;
         }
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) hist_add(bhist[wave], bk[k], bk[k] < (uint32_t)kRadix);
     }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {  // all loads first
@@ -115,12 +132,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t
         }
     }
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const bool valid = dig[k] < kRadix;
-        const uint32_t d = valid ? dig[k] : 0u;
-        const uint64_t peers = match_digit8(d, __ballot(valid));
-        if (valid && (peers & lanemask_lt()) == 0) hist[wave][d] += (uint32_t)__popcll(peers);
-    }
+    for (int k = 0; k < kItems; ++k) hist_add(hist[wave], dig[k], dig[k] < (uint32_t)kRadix);
     __syncthreads();
     uint32_t tot = 0;
 #pragma unroll
@@ -410,12 +422,7 @@ __global__ __launch_bounds__(kThreads) void k_fine_hist(const uint32_t *pair_id,
         dig[k] = i < n ? (pair_id[i] >> fshift) & fmask : (uint32_t)kRadix;
     }
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const bool valid = dig[k] < (uint32_t)kRadix;
-        const uint32_t d = valid ? dig[k] : 0u;
-        const uint64_t peers = match_digit8(d, __ballot(valid));
-        if (valid && (peers & lanemask_lt()) == 0) hist[wave][d] += (uint32_t)__popcll(peers);
-    }
+    for (int k = 0; k < kItems; ++k) hist_add(hist[wave], dig[k], dig[k] < (uint32_t)kRadix);
     __syncthreads();
     if (tid <= (int)fmask) {
         uint32_t tot = 0;
