@@ -184,9 +184,10 @@ def main():
     order_t = torch.empty(values.shape, dtype=torch.int32, device=dev)
     rec = torch.empty((owned, 4), dtype=torch.int32, device=dev)
     flags = dms.new_flags(dev)
+    gws = dms.gradient_workspace(order_t, lo, hi)
     # capacities from one exact run (the counts do not change between steps)
     dms.order(values, out=order_t)
-    dms.discrete_gradient(order_t, lo, hi, out=rec)
+    dms.discrete_gradient(order_t, lo, hi, out=rec, workspace=gws)
     lists, counts = dms.critical_simplices(rec, dims, lo, hi)
     cap = counts.cpu().numpy().copy()
     counts_t = torch.zeros(4, dtype=torch.int64, device=dev)
@@ -197,7 +198,7 @@ def main():
         dms.order(values, out=order_t, flags=flags, check=False)
         if ev is not None:
             ev[1].record(stream)
-        dms.discrete_gradient(order_t, lo, hi, out=rec)
+        dms.discrete_gradient(order_t, lo, hi, out=rec, workspace=gws)
         if ev is not None:
             ev[2].record(stream)
         dms.critical_simplices(rec, dims, lo, hi, cap=cap, flags=flags, counts=counts_t)

@@ -109,11 +109,18 @@ int dms_order(const void *values, int dtype, int64_t n, int32_t *order, void *wo
  * order: int32 of the whole grid (dims), a permutation of 0..n-1 or any
  * injective int32 labelling with the same relative order (values must be
  * < 2^31 - 1).  An empty box is allowed and enqueues nothing.
- * Errors: DMS_E_ARG (null pointer, dims < 1, box outside the grid),
- * DMS_E_SIZE, DMS_E_HIP.
+ * workspace: dms_gradient_workspace_size(dims, lo, hi) bytes (about one
+ * byte per box vertex) holding a queue through which vertices whose lower
+ * star needs the full pairing loop are gathered and paired in dense waves;
+ * or NULL (with workspace_bytes 0), in which case they are paired where
+ * they are found -- the same records, slower on smooth fields.
+ * Errors: DMS_E_ARG (null order/rec, dims < 1, box outside the grid),
+ * DMS_E_SIZE, DMS_E_WORKSPACE (non-null workspace below the size), DMS_E_HIP.
  * -------------------------------------------------------------------------- */
+size_t dms_gradient_workspace_size(const int64_t dims[3], const int64_t lo[3], const int64_t hi[3]);
 int dms_discrete_gradient(const int32_t *order, const int64_t dims[3], const int64_t lo[3],
-                          const int64_t hi[3], uint32_t *rec, void *stream);
+                          const int64_t hi[3], uint32_t *rec, void *workspace,
+                          size_t workspace_bytes, void *stream);
 
 /* ----------------------------------------------------------------------------
  * Critical simplices -- Section 2.6 (zero-persistence skip: every

@@ -23,7 +23,8 @@ STATUS = {0: "DMS_OK", 1: "DMS_E_ARG", 2: "DMS_E_SIZE", 3: "DMS_E_WORKSPACE",
 
 # every symbol include/dms.h declares
 SYMBOLS = ("dms_status_str", "dms_version", "dms_star_tables", "dms_order_workspace_size",
-           "dms_order", "dms_discrete_gradient", "dms_critical_workspace_size",
+           "dms_order", "dms_gradient_workspace_size", "dms_discrete_gradient",
+           "dms_critical_workspace_size",
            "dms_critical_simplices", "dms_gradient_backward", "dms_d0_pairs_host",
            "dms_batch_create", "dms_batch_workspace_size", "dms_batch_total", "dms_batch_variant",
            "dms_batch_run", "dms_batch_destroy")
@@ -55,7 +56,9 @@ def lib():
     L.dms_order_workspace_size.argtypes = [I64, I]
     L.dms_order_workspace_size.restype = SZ
     L.dms_order.argtypes = [P, I, I64, P, P, SZ, P, P]
-    L.dms_discrete_gradient.argtypes = [P, P, P, P, P, P]
+    L.dms_gradient_workspace_size.argtypes = [P, P, P]
+    L.dms_gradient_workspace_size.restype = SZ
+    L.dms_discrete_gradient.argtypes = [P, P, P, P, P, P, SZ, P]
     L.dms_critical_workspace_size.argtypes = [P, P, P]
     L.dms_critical_workspace_size.restype = SZ
     L.dms_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
@@ -193,9 +196,23 @@ def _box(dims, lo, hi):
     return lo, hi
 
 
-def discrete_gradient(order_t, lo=None, hi=None, out=None):
+def gradient_workspace(order_t, lo=None, hi=None):
+    """A workspace for discrete_gradient on this grid and box (uint8 tensor)."""
+    import torch
+    dims = dims_of(order_t)
+    lo, hi = _box(dims, lo, hi)
+    d, dp = _arr3(dims)
+    l, lp = _arr3(lo)
+    h, hp = _arr3(hi)
+    return torch.empty(max(int(lib().dms_gradient_workspace_size(dp, lp, hp)), 256),
+                       dtype=torch.uint8, device=order_t.device)
+
+
+def discrete_gradient(order_t, lo=None, hi=None, out=None, queue=True, workspace=None):
     """Lower-star records (dms_discrete_gradient): int32 tensor (nbox, 4)
-    holding the 128-bit records (reinterpret as uint32)."""
+    holding the 128-bit records (reinterpret as uint32).  queue=False passes
+    no workspace (general vertices are then paired inside their tiles);
+    workspace (from gradient_workspace) avoids an allocation per call."""
     import torch
     _require_gpu(order_t, "order")
     if order_t.dtype != torch.int32:
@@ -208,7 +225,19 @@ def discrete_gradient(order_t, lo=None, hi=None, out=None):
     d, dp = _arr3(dims)
     l, lp = _arr3(lo)
     h, hp = _arr3(hi)
-    _check(lib().dms_discrete_gradient(_ptr(order_t), dp, lp, hp, _ptr(out), _stream(order_t)),
+    ws, wbytes = None, 0
+    if queue and nbox > 0:
+        wbytes = int(lib().dms_gradient_workspace_size(dp, lp, hp))
+        if workspace is not None:
+            if workspace.numel() < wbytes or not workspace.is_cuda:
+                raise ValueError("gradient workspace too small (%d < %d bytes)"
+                                 % (workspace.numel(), wbytes))
+            ws, wbytes = workspace, workspace.numel()
+        else:
+            ws = torch.empty(wbytes, dtype=torch.uint8, device=order_t.device)
+    _check(lib().dms_discrete_gradient(_ptr(order_t), dp, lp, hp, _ptr(out),
+                                       _ptr(ws) if ws is not None else None, wbytes,
+                                       _stream(order_t)),
            "dms_discrete_gradient")
     return out
 

@@ -77,7 +77,7 @@ void cache_store(const std::string &path, uint64_t sig, int variant)
 }
 
 struct Ws {
-    char *order, *crit;
+    char *order, *crit, *grad;
 };
 
 Ws carve(const dms_batch *b, void *ws)
@@ -85,6 +85,7 @@ Ws carve(const dms_batch *b, void *ws)
     Ws w;
     w.order = (char *)ws;
     w.crit = w.order + dms::align_up(dms::order_batch_workspace_size(b->total), 256);
+    w.grad = w.crit + dms::align_up(dms::critical_batch_workspace_size(b->total, b->nfields), 256);
     return w;
 }
 
@@ -105,14 +106,15 @@ int enqueue_all(dms_batch *b, const void *values, int32_t *order, uint32_t *rec,
                                      w.order, flags, s);
     if (st) return st;
     st = dms::launch_gradient_batch(b->variant, order, b->d_fields, b->nfields, b->d_tiles[b->variant],
-                                    b->tiles[b->variant], rec, dms::gradient_batch_grid(b->variant), s);
+                                    b->tiles[b->variant], b->total, rec,
+                                    dms::gradient_batch_grid(b->variant), w.grad, s);
     if (st) return st;
     return dms::launch_critical_batch(rec, b->total, b->d_off, b->nfields, b->d_fields, crit, cap,
                                       counts, offsets, w.crit, flags, s);
 }
 
 // Times each tile shape on the caller's data (the order must be ready).
-int autotune(dms_batch *b, const int32_t *order, uint32_t *rec, hipStream_t s)
+int autotune(dms_batch *b, const int32_t *order, uint32_t *rec, char *gws, hipStream_t s)
 {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DMS_E_HIP;
@@ -123,7 +125,7 @@ int autotune(dms_batch *b, const int32_t *order, uint32_t *rec, hipStream_t s)
         for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
             int st = dms::launch_gradient_batch(v, order, b->d_fields, b->nfields, b->d_tiles[v], b->tiles[v],
-                                                rec, dms::gradient_batch_grid(v), s);
+                                                b->total, rec, dms::gradient_batch_grid(v), gws, s);
             (void)hipEventRecord(e1, s);
             if (st) return st;
             if (hipEventSynchronize(e1) != hipSuccess) return DMS_E_HIP;
@@ -210,7 +212,8 @@ extern "C" size_t dms_batch_workspace_size(const dms_batch *b)
 {
     if (!b) return 0;
     return dms::align_up(dms::order_batch_workspace_size(b->total), 256) +
-           dms::critical_batch_workspace_size(b->total, b->nfields);
+           dms::align_up(dms::critical_batch_workspace_size(b->total, b->nfields), 256) +
+           dms::gradient_workspace_size(b->total);
 }
 
 extern "C" int64_t dms_batch_total(const dms_batch *b) { return b ? b->total : -1; }
@@ -234,7 +237,7 @@ extern "C" int dms_batch_run(dms_batch *b, const void *values, int32_t *order, u
         int st = dms::launch_order_batch((const float *)values, b->total, b->d_off, b->nfields, order,
                                          w.order, dev_flags, s);
         if (st) return st;
-        st = autotune(b, order, rec, s);
+        st = autotune(b, order, rec, w.grad, s);
         if (st) return st;
         b->tuned = true;
         destroy_graph(b);

@@ -100,30 +100,10 @@ __device__ __forceinline__ uint64_t lower_star_tq(uint32_t low)
     return ~out_tq & ((1ull << 60) - 1);
 }
 
-// Robins' ProcessLowerStars for one vertex, from the orders of x and its 14
-// neighbours (kAbsent for neighbours outside the grid).  mmax is an upper
-// bound, uniform over the wave, of the number of lower neighbours.
-//
-// The two priority queues of Robins' formulation are not stored: at any time
-// the one-facet queue, minus entries that have meanwhile lost their last
-// unpaired facet, is exactly the set of unpaired cells with one unpaired
-// facet (every cell enters it at the moment its count drops from two to
-// one), and when that set is empty the zero queue's live entries are exactly
-// the unpaired edges and the unpaired cells with no unpaired facet.  So each
-// step takes the smallest cell of the first set and pairs it with its
-// unpaired facet, or, if that set is empty, declares the smallest cell of the
-// second set critical.  "Smallest" is a bit-sliced minimum over key planes:
-// plane b holds the cells that contain the neighbour of rank b, and the key
-// of a cell is the integer with those bits (Section 2.1 comparison).
-__device__ __forceinline__ void process_vertex(const int32_t *o, int32_t ox, int mmax, const SharedTables &T,
-                               uint4 &out)
+// Ranks of the lower neighbours among themselves, 4 bits per neighbour
+// (15 for a neighbour that is not lower).
+__device__ __forceinline__ uint64_t lower_ranks(const int32_t *o, uint32_t low)
 {
-    const uint32_t low = lower_mask(o, ox);
-    if (low == 0) {  // L(x) = {x}: x is critical
-        out = make_uint4(0, 0, 0, 0);
-        return;
-    }
-    // ranks among the lower neighbours (non-lower ones rank above them)
     uint32_t ol[14], r[14];
 #pragma unroll
     for (int e = 0; e < 14; ++e) {
@@ -138,12 +118,61 @@ __device__ __forceinline__ void process_vertex(const int32_t *o, int32_t ox, int
             r[a] += c;
             r[b] += 1u - c;
         }
-    uint64_t nb_at = 0, rank_of = 0;  // rank -> neighbour, neighbour -> rank (4 bits each)
+    uint64_t rank_of = 0;
 #pragma unroll
-    for (int e = 0; e < 14; ++e) {
-        rank_of |= (uint64_t)r[e] << (4 * e);
-        if ((low >> e) & 1u) nb_at |= (uint64_t)e << (4 * r[e]);
+    for (int e = 0; e < 14; ++e) rank_of |= (uint64_t)((low >> e) & 1u ? r[e] : 15u) << (4 * e);
+    return rank_of;
+}
+
+__device__ __forceinline__ uint32_t low_of_ranks(uint64_t rank_of)
+{
+    uint32_t low = 0;
+#pragma unroll
+    for (int e = 0; e < 14; ++e) low |= (nib(rank_of, e) != 15u ? 1u : 0u) << e;
+    return low;
+}
+
+__device__ __forceinline__ void robins(uint64_t rank_of, int mmax, const SharedTables &T, uint4 &out);
+
+// Robins' ProcessLowerStars for one vertex, from the orders of x and its 14
+// neighbours (kAbsent for neighbours outside the grid); mmax as in robins.
+__device__ __forceinline__ void process_vertex(const int32_t *o, int32_t ox, int mmax, const SharedTables &T,
+                                               uint4 &out)
+{
+    const uint32_t low = lower_mask(o, ox);
+    if (low == 0) {  // L(x) = {x}: x is critical
+        out = make_uint4(0, 0, 0, 0);
+        return;
     }
+    robins(lower_ranks(o, low), mmax, T, out);
+}
+
+// The pairing itself, from the ranks of the lower neighbours (lower_ranks).
+// mmax is an upper bound, uniform over the wave, of the number of lower
+// neighbours.
+//
+// The two priority queues of Robins' formulation are not stored: at any time
+// the one-facet queue, minus entries that have meanwhile lost their last
+// unpaired facet, is exactly the set of unpaired cells with one unpaired
+// facet (every cell enters it at the moment its count drops from two to
+// one), and when that set is empty the zero queue's live entries are exactly
+// the unpaired edges and the unpaired cells with no unpaired facet.  So each
+// step takes the smallest cell of the first set and pairs it with its
+// unpaired facet, or, if that set is empty, declares the smallest cell of the
+// second set critical.  "Smallest" is a bit-sliced minimum over key planes:
+// plane b holds the cells that contain the neighbour of rank b, and the key
+// of a cell is the integer with those bits (Section 2.1 comparison).
+__device__ __forceinline__ void robins(uint64_t rank_of, int mmax, const SharedTables &T, uint4 &out)
+{
+    const uint32_t low = low_of_ranks(rank_of);
+    if (low == 0) {
+        out = make_uint4(0, 0, 0, 0);
+        return;
+    }
+    uint64_t nb_at = 0;  // rank -> neighbour (4 bits each)
+#pragma unroll
+    for (int e = 0; e < 14; ++e)
+        if ((low >> e) & 1u) nb_at |= (uint64_t)e << (4 * nib(rank_of, e));
     const int m = __popc(low);
     // complement of the key planes: nkp[b] = TQ cells NOT containing rank b
     uint64_t nkp[14];
@@ -362,9 +391,21 @@ __device__ __forceinline__ void gather_orders(const int32_t *tile, int c, int32_
         o[e] = tile[c + kTables.nb[e][0] + S::HX * (kTables.nb[e][1] + S::HY * kTables.nb[e][2])];
 }
 
+// Vertices that no table covers ("general" vertices) need Robins' loop,
+// whose length varies with the lower star.  A tile with many of them pairs
+// them itself, dealt to threads by increasing size (pass 2).  A tile with
+// few -- the common case of a smooth field -- would leave one sparse wave
+// running a long loop while the block holds its slot, so it ranks them and
+// appends compact entries to a device queue instead; a second kernel pairs
+// the queue in full waves sorted by size.
+//   entry: x, y = ranks of the lower neighbours (lower_ranks), z = record
+//          index, w = size key.
+constexpr int kQueueChunk = 1024;  // entries per block of the queue kernel
+
 struct BlockShared {
     SharedTables T;
     uint32_t bins[kSizeBins];
+    uint32_t qbase;
     uint16_t perm[kTileVerts];
     uint8_t key[kTileVerts];
 };
@@ -376,19 +417,40 @@ __device__ __forceinline__ void load_tables(SharedTables &T)
     for (int i = threadIdx.x; i < (int)(sizeof(SharedTables) / 4); i += kThreads) dst[i] = src[i];
 }
 
+// Exclusive scan of sh.bins (kSizeBins <= 2 * kWave) by the first wave.
+__device__ __forceinline__ void scan_bins(uint32_t *bins)
+{
+    const int tid = threadIdx.x;
+    if (tid < kWave) {
+        const uint32_t v0 = tid < kSizeBins ? bins[tid] : 0u;
+        const uint32_t v1 = tid + kWave < kSizeBins ? bins[tid + kWave] : 0u;
+        uint32_t i0 = v0, i1 = v1;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t t0 = __shfl_up(i0, off), t1 = __shfl_up(i1, off);
+            if (tid >= off) { i0 += t0; i1 += t1; }
+        }
+        const uint32_t tot0 = __shfl(i0, kWave - 1);
+        if (tid < kSizeBins) bins[tid] = i0 - v0;
+        if (tid + kWave < kSizeBins) bins[tid + kWave] = tot0 + i1 - v1;
+    }
+}
+
 // One GX x GY x 1 tile (1024 vertices) of the owned box [lo, lo + w) of a
-// grid of dims n.  The orders of the tile plus a one-vertex halo are staged
-// in LDS.  Pass 1 visits the tile in order (4 vertices per thread): a
-// regular or one-defect vertex takes its record from the precomputed
-// tables; any other vertex is binned by the size of its lower star.  Pass 2 deals those vertices to threads by increasing size, so that
-// the vertices of a wave need similar numbers of steps (a wave runs as long
-// as its slowest lane).  Must be entered by the whole block.
+// grid of dims n; record indices are rec_off + position in the owned box.
+// The orders of the tile plus a one-vertex halo are staged in LDS.  Pass 1
+// visits the tile in order (4 vertices per thread): a regular or one-defect
+// vertex takes its record from the precomputed tables; any other vertex is
+// binned by the size of its lower star.  Those are then queued (fewer than a
+// block's worth, while the queue has room) or paired here by increasing size.
+// Must be entered by the whole block.
 template <int GX, int GY>
 __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order, int64_t nx,
                                               int64_t ny, int64_t nz, int64_t lo0, int64_t lo1,
                                               int64_t lo2, int64_t w0, int64_t w1, int64_t w2,
-                                              int64_t bx, int64_t by, int64_t bz,
+                                              int64_t bx, int64_t by, int64_t bz, int64_t rec_off,
                                               uint4 *__restrict__ rec, const uint4 *__restrict__ defect8,
+                                              uint4 *__restrict__ queue, uint32_t *qcount, uint32_t qcap,
                                               BlockShared &sh, int32_t *tile)
 {
     using S = Tile<GX, GY>;
@@ -407,8 +469,8 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
     }
     __syncthreads();
 
-    // pass 1: regular vertices from the table; others get a size key
-    const int64_t rbase = (bx * GX) + w0 * ((by * GY) + w1 * bz);
+    // pass 1: table vertices; the others get a size key
+    const int64_t rbase = rec_off + (bx * GX) + w0 * ((by * GY) + w1 * bz);
 #pragma unroll
     for (int k = 0; k < kTileVerts / kThreads; ++k) {
         const int v = tid + k * kThreads;
@@ -430,21 +492,9 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
         sh.key[v] = (uint8_t)(key < kSizeBins ? key : 0xffu);
     }
     __syncthreads();
-    if (tid < kWave) {  // exclusive scan of the bins by the first wave
-        const uint32_t v0 = tid < kSizeBins ? sh.bins[tid] : 0u;
-        const uint32_t v1 = tid + kWave < kSizeBins ? sh.bins[tid + kWave] : 0u;
-        uint32_t i0 = v0, i1 = v1;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint32_t t0 = __shfl_up(i0, off), t1 = __shfl_up(i1, off);
-            if (tid >= off) { i0 += t0; i1 += t1; }
-        }
-        const uint32_t tot0 = __shfl(i0, kWave - 1);
-        if (tid < kSizeBins) sh.bins[tid] = i0 - v0;
-        if (tid + kWave < kSizeBins) sh.bins[tid + kWave] = tot0 + i1 - v1;
-    }
+    scan_bins(sh.bins);
     __syncthreads();
-    // deal the irregular vertices into perm by key (within a key any order)
+    // deal the general vertices into perm by key (within a key any order)
 #pragma unroll
     for (int k = 0; k < kTileVerts / kThreads; ++k) {
         const int v = tid + k * kThreads;
@@ -454,9 +504,33 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
     __syncthreads();
     // the last bin is never used (keys are at most 75): its start is the total
     const uint32_t total = sh.bins[kSizeBins - 1];
+    if (total == 0) return;
 
-    // pass 2: irregular vertices by increasing lower-star size
-    for (uint32_t base = 0; base < total; base += kThreads) {
+    // queue the first nq (smallest) of them: as many as fit below qcap, so
+    // that every slot the queue kernel reads, [0, min(count, qcap)), has been
+    // written by this launch; the rest are paired here
+    uint32_t nq = 0;
+    if (queue && total < (uint32_t)kThreads) {
+        if (tid == 0) sh.qbase = atomicAdd(qcount, total);
+        __syncthreads();
+        const uint32_t qb = sh.qbase;
+        nq = qb >= qcap ? 0u : min(total, qcap - qb);  // uniform
+        if ((uint32_t)tid < nq) {
+            const int v = sh.perm[tid];
+            const int tx = v % GX, ty = v / GX;
+            const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
+            int32_t o[14];
+            gather_orders<GX, GY>(tile, c, o);
+            const uint32_t low = lower_mask(o, tile[c]);
+            const uint64_t rk = lower_ranks(o, low);
+            queue[qb + tid] = make_uint4((uint32_t)rk, (uint32_t)(rk >> 32),
+                                         (uint32_t)(rbase + tx + w0 * ty), sh.key[v]);
+        }
+        if (nq == total) return;
+    }
+
+    // pass 2: general vertices by increasing lower-star size
+    for (uint32_t base = nq; base < total; base += kThreads) {
         const uint32_t i = base + tid;
         const bool active = i < total;
         const int v = active ? sh.perm[i] : 0;
@@ -478,21 +552,23 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
 }
 
 template <int GX, int GY>
-__global__ __launch_bounds__(kThreads) void k_gradient(const int32_t *__restrict__ order,
+__global__ __launch_bounds__(kThreads, 8) void k_gradient(const int32_t *__restrict__ order,
                                                        int64_t nx, int64_t ny, int64_t nz,
                                                        int64_t lo0, int64_t lo1, int64_t lo2,
                                                        int64_t w0, int64_t w1, int64_t w2,
                                                        int64_t bx_count, int64_t by_count,
                                                        uint4 *__restrict__ rec,
-                                                       const uint4 *__restrict__ defect8)
+                                                       const uint4 *__restrict__ defect8,
+                                                       uint4 *__restrict__ queue, uint32_t *qcount,
+                                                       uint32_t qcap)
 {
     __shared__ BlockShared sh;
     __shared__ int32_t tile[Tile<GX, GY>::kHalo];
     load_tables(sh.T);
     const int64_t b = blockIdx.x;
     const int64_t bx = b % bx_count, by = (b / bx_count) % by_count, bz = b / (bx_count * by_count);
-    gradient_tile<GX, GY>(order, nx, ny, nz, lo0, lo1, lo2, w0, w1, w2, bx, by, bz, rec, defect8, sh,
-                          tile);
+    gradient_tile<GX, GY>(order, nx, ny, nz, lo0, lo1, lo2, w0, w1, w2, bx, by, bz, 0, rec, defect8,
+                          queue, qcount, qcap, sh, tile);
 }
 
 // Batched form: many whole fields, concatenated; a persistent grid walks the
@@ -502,7 +578,9 @@ __global__ __launch_bounds__(kThreads, 5) void k_gradient_batch(const int32_t *_
                                                                 const BatchField *__restrict__ fields,
                                                                 int nfields, const int64_t *tile_start,
                                                                 uint4 *__restrict__ rec,
-                                                                const uint4 *__restrict__ defect8)
+                                                                const uint4 *__restrict__ defect8,
+                                                                uint4 *__restrict__ queue,
+                                                                uint32_t *qcount, uint32_t qcap)
 {
     __shared__ BlockShared sh;
     __shared__ int32_t tile[Tile<GX, GY>::kHalo];
@@ -523,8 +601,54 @@ __global__ __launch_bounds__(kThreads, 5) void k_gradient_batch(const int32_t *_
         const int64_t k = t - tstart[lo];
         const int64_t bx = k % bxc, by = (k / bxc) % byc, bz = k / (bxc * byc);
         gradient_tile<GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1], F.n[2],
-                              bx, by, bz, rec + F.off, defect8, sh, tile);
+                              bx, by, bz, F.off, rec, defect8, queue, qcount, qcap, sh, tile);
         __syncthreads();  // the next tile reuses the shared buffers
+    }
+}
+
+__global__ void k_queue_reset(uint32_t *qcount) { *qcount = 0; }
+
+// Pairs the queued general vertices: block b takes entries
+// [b kQueueChunk, (b+1) kQueueChunk) of the filled part, sorts them by size
+// key and runs Robins' loop on them in full rounds.
+__global__ __launch_bounds__(kThreads) void k_gradient_queue(const uint4 *__restrict__ queue,
+                                                             const uint32_t *qcount, uint32_t qcap,
+                                                             uint4 *__restrict__ rec)
+{
+    __shared__ SharedTables T;
+    __shared__ uint32_t bins[kSizeBins];
+    __shared__ uint16_t perm[kQueueChunk];
+    const int tid = threadIdx.x;
+    const uint32_t filled = min(*qcount, qcap);
+    const uint64_t start = (uint64_t)blockIdx.x * kQueueChunk;
+    if (start >= filled) return;  // uniform
+    const uint32_t cnt = (uint32_t)min<uint64_t>(kQueueChunk, filled - start);
+    load_tables(T);
+    for (int i = tid; i < kSizeBins; i += kThreads) bins[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < cnt; i += kThreads) atomicAdd(&bins[min(queue[start + i].w, (uint32_t)kSizeBins - 1u)], 1u);
+    __syncthreads();
+    scan_bins(bins);
+    __syncthreads();
+    for (uint32_t i = tid; i < cnt; i += kThreads)
+        perm[atomicAdd(&bins[min(queue[start + i].w, (uint32_t)kSizeBins - 1u)], 1u)] = (uint16_t)i;
+    __syncthreads();
+    for (uint32_t base = 0; base < cnt; base += kThreads) {
+        const uint32_t i = base + tid;
+        const bool active = i < cnt;
+        uint4 e = make_uint4(0xffffffffu, 0x00ffffffu, 0u, 0u);  // no lower neighbour
+        if (active) e = queue[start + perm[i]];
+        const uint64_t rk = (uint64_t)e.x | (uint64_t)e.y << 32;
+        const int m = __popc(low_of_ranks(rk));
+        int mmax = m;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
+        mmax = __builtin_amdgcn_readfirstlane(mmax);
+        if (active) {
+            uint4 r;
+            robins(rk, mmax, T, r);
+            rec[e.z] = r;
+        }
     }
 }
 
@@ -652,48 +776,6 @@ static const uint4 *defect8_table()
     return (g_regular_ready.load() >> dev) & 1u ? g_defect8_ptr[dev] : nullptr;
 }
 
-int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
-                    const int64_t *hi, uint32_t *rec, hipStream_t s)
-{
-    const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
-    if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
-    const int gx = kTileX[variant], gy = kTileVerts / gx;
-    const int64_t bxc = (w0 + gx - 1) / gx, byc = (w1 + gy - 1) / gy;
-    const int64_t blocks = bxc * byc * w2;
-    if (blocks > 2147483647LL) return DMS_E_SIZE;
-    const uint4 *d8 = defect8_table();
-#define DMS_LAUNCH(GXV)                                                                              \
-    hipLaunchKernelGGL((k_gradient<GXV, kTileVerts / GXV>), dim3((unsigned)blocks), dim3(kThreads), 0, s, \
-                       order, dims[0], dims[1], dims[2], lo[0], lo[1], lo[2], w0, w1, w2, bxc, byc,  \
-                       (uint4 *)rec, d8)
-    switch (variant) {
-    case 0: DMS_LAUNCH(64); break;
-    case 1: DMS_LAUNCH(32); break;
-    default: DMS_LAUNCH(16); break;
-    }
-#undef DMS_LAUNCH
-    return launch_status();
-}
-
-int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
-                          const int64_t *tile_start, int64_t total_tiles, uint32_t *rec, int grid,
-                          hipStream_t s)
-{
-    if (total_tiles == 0) return DMS_OK;
-    const unsigned g = (unsigned)(total_tiles < grid ? total_tiles : grid);
-    const uint4 *d8 = defect8_table();
-#define DMS_LAUNCH(GXV)                                                                          \
-    hipLaunchKernelGGL((k_gradient_batch<GXV, kTileVerts / GXV>), dim3(g), dim3(kThreads), 0, s,  \
-                       order, fields, nfields, tile_start, (uint4 *)rec, d8)
-    switch (variant) {
-    case 0: DMS_LAUNCH(64); break;
-    case 1: DMS_LAUNCH(32); break;
-    default: DMS_LAUNCH(16); break;
-    }
-#undef DMS_LAUNCH
-    return launch_status();
-}
-
 int gradient_batch_grid(int variant)
 {
     int dev = 0, cus = 0, per = 0;
@@ -709,10 +791,103 @@ int gradient_batch_grid(int variant)
     return cus * per;
 }
 
+// Queue of general vertices: a counter, then qcap 16-byte entries; room for
+// one vertex in 16 plus a chunk.
+static uint32_t queue_cap(int64_t owned)
+{
+    const int64_t c = owned / 16 + kQueueChunk;
+    return (uint32_t)(c < 0x7fffffffLL ? c : 0x7fffffffLL);
+}
+
+size_t gradient_workspace_size(int64_t owned) { return 256 + (size_t)queue_cap(owned) * sizeof(uint4); }
+
+// Resets the queue counter; returns (queue, counter, capacity) carved from ws
+// (all null / 0 when ws is null: every tile then pairs its own vertices).
+static void queue_begin(char *ws, int64_t owned, hipStream_t s, uint4 **queue, uint32_t **qcount,
+                        uint32_t *qcap)
+{
+    *queue = nullptr;
+    *qcount = nullptr;
+    *qcap = 0;
+    if (!ws) return;
+    *qcount = (uint32_t *)ws;
+    *queue = (uint4 *)(ws + 256);
+    *qcap = queue_cap(owned);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, s, *qcount);
+}
+
+static void queue_finish(const uint4 *queue, const uint32_t *qcount, uint32_t qcap, uint32_t *rec,
+                         hipStream_t s)
+{
+    if (!queue) return;
+    const unsigned blocks = (unsigned)((qcap + kQueueChunk - 1) / kQueueChunk);
+    hipLaunchKernelGGL(k_gradient_queue, dim3(blocks), dim3(kThreads), 0, s, queue, qcount, qcap,
+                       (uint4 *)rec);
+}
+
+int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
+                    const int64_t *hi, uint32_t *rec, char *ws, hipStream_t s)
+{
+    const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
+    if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
+    const int gx = kTileX[variant], gy = kTileVerts / gx;
+    const int64_t bxc = (w0 + gx - 1) / gx, byc = (w1 + gy - 1) / gy;
+    const int64_t blocks = bxc * byc * w2;
+    if (blocks > 2147483647LL) return DMS_E_SIZE;
+    const uint4 *d8 = defect8_table();
+    uint4 *queue;
+    uint32_t *qcount, qcap;
+    queue_begin(ws, w0 * w1 * w2, s, &queue, &qcount, &qcap);
+#define DMS_LAUNCH(GXV)                                                                              \
+    hipLaunchKernelGGL((k_gradient<GXV, kTileVerts / GXV>), dim3((unsigned)blocks), dim3(kThreads), 0, s, \
+                       order, dims[0], dims[1], dims[2], lo[0], lo[1], lo[2], w0, w1, w2, bxc, byc,  \
+                       (uint4 *)rec, d8, queue, qcount, qcap)
+    switch (variant) {
+    case 0: DMS_LAUNCH(64); break;
+    case 1: DMS_LAUNCH(32); break;
+    default: DMS_LAUNCH(16); break;
+    }
+#undef DMS_LAUNCH
+    queue_finish(queue, qcount, qcap, rec, s);
+    return launch_status();
+}
+
+int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
+                          const int64_t *tile_start, int64_t total_tiles, int64_t total_verts,
+                          uint32_t *rec, int grid, char *ws, hipStream_t s)
+{
+    if (total_tiles == 0) return DMS_OK;
+    const unsigned g = (unsigned)(total_tiles < grid ? total_tiles : grid);
+    const uint4 *d8 = defect8_table();
+    uint4 *queue;
+    uint32_t *qcount, qcap;
+    queue_begin(ws, total_verts, s, &queue, &qcount, &qcap);
+#define DMS_LAUNCH(GXV)                                                                          \
+    hipLaunchKernelGGL((k_gradient_batch<GXV, kTileVerts / GXV>), dim3(g), dim3(kThreads), 0, s,  \
+                       order, fields, nfields, tile_start, (uint4 *)rec, d8, queue, qcount, qcap)
+    switch (variant) {
+    case 0: DMS_LAUNCH(64); break;
+    case 1: DMS_LAUNCH(32); break;
+    default: DMS_LAUNCH(16); break;
+    }
+#undef DMS_LAUNCH
+    queue_finish(queue, qcount, qcap, rec, s);
+    return launch_status();
+}
+
 }  // namespace dms
 
+extern "C" size_t dms_gradient_workspace_size(const int64_t dims[3], const int64_t lo[3],
+                                              const int64_t hi[3])
+{
+    using namespace dms;
+    if (!box_valid(dims, lo, hi) || !grid_size_ok(dims)) return 0;
+    return gradient_workspace_size((hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]));
+}
+
 extern "C" int dms_discrete_gradient(const int32_t *order, const int64_t dims[3], const int64_t lo[3],
-                                     const int64_t hi[3], uint32_t *rec, void *stream)
+                                     const int64_t hi[3], uint32_t *rec, void *workspace,
+                                     size_t workspace_bytes, void *stream)
 {
     using namespace dms;
     if (!box_valid(dims, lo, hi)) return DMS_E_ARG;
@@ -720,7 +895,8 @@ extern "C" int dms_discrete_gradient(const int32_t *order, const int64_t dims[3]
     const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
     if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
     if (!order || !rec) return DMS_E_ARG;
+    if (workspace && workspace_bytes < gradient_workspace_size(w0 * w1 * w2)) return DMS_E_WORKSPACE;
     const int st = ensure_regular_table((hipStream_t)stream);
     if (st) return st;
-    return launch_gradient(0, order, dims, lo, hi, rec, (hipStream_t)stream);
+    return launch_gradient(0, order, dims, lo, hi, rec, (char *)workspace, (hipStream_t)stream);
 }

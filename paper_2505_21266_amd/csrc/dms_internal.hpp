@@ -22,12 +22,15 @@ constexpr int kTileX[kGradVariants] = {64, 32, 16};
 
 // Fills the device's regular-vertex table on first use (one synchronisation).
 int ensure_regular_table(hipStream_t s);
+// ws: gradient_workspace_size(owned vertices) bytes for the queue of
+// general vertices, or null (every tile then pairs its own).
+size_t gradient_workspace_size(int64_t owned);
 int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
-                    const int64_t *hi, uint32_t *rec, hipStream_t s);
+                    const int64_t *hi, uint32_t *rec, char *ws, hipStream_t s);
 int gradient_batch_grid(int variant);  // persistent grid size (CUs x resident blocks)
 int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
-                          const int64_t *tile_start, int64_t total_tiles, uint32_t *rec, int grid,
-                          hipStream_t s);
+                          const int64_t *tile_start, int64_t total_tiles, int64_t total_verts,
+                          uint32_t *rec, int grid, char *ws, hipStream_t s);
 
 // Batched order: values of all fields concatenated (float32); the field of
 // element i is the f with foff[f] <= i < foff[f + 1] (foff on the device).

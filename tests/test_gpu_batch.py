@@ -80,6 +80,27 @@ def test_batch_graph_replay():
     _check_fields(SIDES, fields, *again)
 
 
+def test_batch_alternating_inputs():
+    """Two different batches of values through one plan and one set of
+    buffers, alternating: every run equals the oracle (nothing carries over
+    from the previous run, e.g. through the queue of general vertices)."""
+    fa = [_field(s, i % 3, 400 + i) for i, s in enumerate(SIDES)]
+    fb = [_field(s, (i + 1) % 3, 500 + i) for i, s in enumerate(SIDES)]
+    va = torch.from_numpy(np.concatenate([f.reshape(-1) for f in fa])).cuda()
+    vb = torch.from_numpy(np.concatenate([f.reshape(-1) for f in fb])).cuda()
+    b = dms.Batch(SIDES)
+    cap = [1 << 16] * 4
+    bufs = b._alloc(cap)
+    for rep, (vals, fields) in enumerate([(va, fa), (vb, fb), (va, fa), (vb, fb)]):
+        bufs["rec"].fill_(-1)
+        bufs["flags"].zero_()
+        b.launch(vals, bufs)
+        dms.check_flags(bufs["flags"])
+        out = (bufs["order"], bufs["rec"], bufs["lists"], bufs["counts"].view(b.nfields, 4),
+               bufs["offsets"].view(4, b.nfields + 1))
+        _check_fields(SIDES, fields, *out)
+
+
 def test_batch_autotune_cache(tmp_path):
     path = str(tmp_path / "tune.txt")
     sides = SIDES[:6]

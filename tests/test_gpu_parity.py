@@ -168,6 +168,25 @@ def test_gradient_records(dims, kind, seed):
     assert (got2 == want).all()
 
 
+def test_gradient_queue_paths():
+    """A tilted ramp plus noise (about 15% of vertices outside the tables):
+    interior tiles queue their general vertices until the queue (one vertex
+    in 16) overflows, later ones pair them in place, the boundary planes'
+    tiles are dense and pair in place too.  With and without the queue the
+    records equal the oracle's."""
+    nz, ny, nx = 40, 96, 160
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    v = (i + 1.37 * j + 1.91 * k + 2.5 * np.random.default_rng(5).random((nz, ny, nx)))
+    v = v.astype(np.float32)
+    o = oracle.order(v)
+    want, _, _ = oracle.lower_stars(o, (nx, ny, nz))
+    _say("gradient queue paths")
+    og = _dev(o)
+    for queue in (True, False):
+        got = dms.discrete_gradient(og, queue=queue).cpu().numpy().view(np.uint32)
+        assert (got == want).all(), queue
+
+
 @pytest.mark.parametrize("dims,lo,hi", [((20, 18, 16), (1, 2, 1), (19, 17, 15)),
                                         ((66, 10, 7), (1, 1, 1), (65, 9, 6)),
                                         ((30, 30, 30), (0, 0, 0), (30, 1, 30)),

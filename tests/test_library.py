@@ -73,13 +73,17 @@ def test_argument_errors(L):
     assert L.dms_order_workspace_size(1000, 0) >= 16 * 1000
     assert L.dms_order_workspace_size(1000, 1) >= 24 * 1000
     # gradient
-    assert L.dms_discrete_gradient(None, dp, lp, hp, fake, None) == 1
-    assert L.dms_discrete_gradient(fake, dp, lp, badp, fake, None) == 1
+    assert L.dms_discrete_gradient(None, dp, lp, hp, fake, None, 0, None) == 1
+    assert L.dms_discrete_gradient(fake, dp, lp, badp, fake, None, 0, None) == 1
     big, bigp = _a3([2048, 2048, 1024])
-    assert L.dms_discrete_gradient(fake, bigp, lp, hp, fake, None) == 2
-    assert L.dms_discrete_gradient(fake, dp, lp, lp, fake, None) == 0  # empty box
+    assert L.dms_discrete_gradient(fake, bigp, lp, hp, fake, None, 0, None) == 2
+    assert L.dms_discrete_gradient(fake, dp, lp, lp, fake, None, 0, None) == 0  # empty box
     neg, negp = _a3([-1, 0, 0])
-    assert L.dms_discrete_gradient(fake, dp, negp, hp, fake, None) == 1
+    assert L.dms_discrete_gradient(fake, dp, negp, hp, fake, None, 0, None) == 1
+    need = L.dms_gradient_workspace_size(dp, lp, hp)
+    assert need >= 256 + 16 * 1024
+    assert L.dms_discrete_gradient(fake, dp, lp, hp, fake, fake, need - 1, None) == 3
+    assert L.dms_gradient_workspace_size(dp, lp, badp) == 0
     # critical
     cap, capp = _a3([0, 0, 0, 0])
     assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, capp, fake, fake, 0,
