@@ -283,35 +283,6 @@ constexpr int kPerm7 = 5040;
 constexpr int kRegular = 128 * kPerm7;
 __device__ uint4 g_regular[kRegular];
 
-// 7-bit mask: bit i set when the lower member of pair i is neighbour 13 - i;
-// returns false unless exactly one member of every pair is lower.
-__device__ __forceinline__ bool regular_pattern(uint32_t low, uint32_t &side)
-{
-    const uint32_t rev = __brev(low) >> 18;  // bit e -> bit 13 - e
-    side = (low >> 7) & 0x7fu;               // members 7..13, as bits of 13 - e
-    side = __brev(side) >> 25;               // bit (13 - e) - 7 -> bit e' for pair index
-    return ((low ^ rev) & 0x7fu) == 0x7fu;
-}
-
-// Table index of a regular vertex: side pattern x 5040 + Lehmer code of the
-// order of the 7 lower neighbours taken by pair index.
-__device__ __forceinline__ uint32_t regular_index(const int32_t *o, uint32_t side)
-{
-    int32_t v[7];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) v[i] = ((side >> i) & 1u) ? o[13 - i] : o[i];
-    const uint32_t fact[7] = {720, 120, 24, 6, 2, 1, 1};
-    uint32_t code = 0;
-#pragma unroll
-    for (int i = 0; i < 7; ++i) {
-        uint32_t l = 0;
-#pragma unroll
-        for (int j = i + 1; j < 7; ++j) l += v[j] < v[i] ? 1u : 0u;
-        code += l * fact[i];
-    }
-    return side * kPerm7 + code;
-}
-
 // One-defect vertices: six pairs have one lower member and the seventh has
 // both (8 lower neighbours) or neither (6).  The records of these two
 // families are tabulated the same way, by defect pair j, the sides of the
@@ -330,48 +301,48 @@ __device__ uint4 g_defect6[kDefect6];
 
 // Record of x from one of the tables, or null when x is in none of the
 // families (defect8 may be null: that family then takes the general path).
+// One Lehmer computation serves the three families: eight slots v[i] (the
+// lower member of pair i for i < 7, then neighbour j), with a sentinel above
+// every order in the slots a family does not use, so that each digit l_i
+// counts only used slots; the families differ only in the radix of each
+// digit (Horner form of the factorial-base code).
 __device__ __forceinline__ const uint4 *table_entry(uint32_t low, const int32_t *o,
                                                     const uint4 *__restrict__ defect8)
 {
-    uint32_t side;
-    if (regular_pattern(low, side)) return &g_regular[regular_index(o, side)];
-    const uint32_t rev = __brev(low) >> 18;
+    constexpr int32_t kHigh = 0x7fffffff;
+    const uint32_t rev = __brev(low) >> 18;  // bit e -> bit 13 - e
     const uint32_t one = (low ^ rev) & 0x7fu;
-    if (__popc(one) != 6) return nullptr;
-    const uint32_t j = (uint32_t)__ffs(~one & 0x7fu) - 1u;
-    const uint32_t side6 = (side & ((1u << j) - 1u)) | ((side >> (j + 1u)) << j);
+    const int npair = __popc(one);
+    if (npair < 6) return nullptr;
+    const bool regular = npair == 7;
+    uint32_t side = __brev((low >> 7) & 0x7fu) >> 25;  // bit i: the lower member is 13 - i
+    const uint32_t j = regular ? 7u : (uint32_t)__ffs(~one & 0x7fu) - 1u;
+    const bool eight = !regular && ((low >> j) & 1u);  // pair j wholly lower
+    if (eight && !defect8) return nullptr;
+    const bool six = !regular && !eight;               // pair j wholly upper
     int32_t v[8];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) v[i] = ((side >> i) & 1u) ? o[13 - i] : o[i];
-    if ((low >> j) & 1u) {  // pair j wholly lower
-        if (!defect8) return nullptr;
-        int32_t oj = 0;
-#pragma unroll
-        for (int i = 0; i < 7; ++i) oj = (uint32_t)i == j ? o[i] : oj;
-        v[7] = oj;
-        uint32_t code = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            uint32_t l = 0;
-#pragma unroll
-            for (int k = i + 1; k < 8; ++k) l += v[k] < v[i] ? 1u : 0u;
-            code = code * (uint32_t)(8 - i) + l;
-        }
-        return defect8 + ((int64_t)(j * 64u + side6) * kPerm8 + code);
-    }
-    // pair j wholly upper: skip its slot (a sentinel above every order keeps
-    // it out of the other slots' counts)
-#pragma unroll
-    for (int i = 0; i < 7; ++i) v[i] = (uint32_t)i == j ? 0x7fffffff : v[i];
-    uint32_t code = 0;
+    int32_t oj = kHigh;
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
+        const int32_t lowm = ((side >> i) & 1u) ? o[13 - i] : o[i];
+        v[i] = six && (uint32_t)i == j ? kHigh : lowm;
+        oj = (uint32_t)i == j ? o[i] : oj;
+    }
+    v[7] = eight ? oj : kHigh;
+    uint32_t code = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
         uint32_t l = 0;
 #pragma unroll
-        for (int k = i + 1; k < 7; ++k) l += v[k] < v[i] ? 1u : 0u;
-        const uint32_t left = (uint32_t)i > j ? 7u - i : 6u - i;  // slots still to come
-        code = (uint32_t)i == j ? code : code * left + l;
+        for (int k = i + 1; k < 8; ++k) l += v[k] < v[i] ? 1u : 0u;
+        // radix of digit i: the number of used slots from i on
+        const uint32_t radix = eight ? 8u - i : (six && (uint32_t)i > j ? 7u - i : 7u - i - (six ? 1u : 0u));
+        const bool used = eight || (i < 7 && !(six && (uint32_t)i == j));
+        code = used ? code * radix + l : code;
     }
+    if (regular) return &g_regular[side * kPerm7 + code];
+    const uint32_t side6 = (side & ((1u << j) - 1u)) | ((side >> (j + 1u)) << j);
+    if (eight) return defect8 + ((int64_t)(j * 64u + side6) * kPerm8 + code);
     return &g_defect6[(j * 64u + side6) * kPerm6 + code];
 }
 
@@ -406,8 +377,9 @@ struct BlockShared {
     SharedTables T;
     uint32_t bins[kSizeBins];
     uint32_t qbase;
-    uint16_t perm[kTileVerts];
-    uint8_t key[kTileVerts];
+    uint32_t nlist;
+    uint16_t list[kTileVerts];  // general vertices of the tile (tile positions)
+    uint16_t perm[kTileVerts];  // the same, sorted by size key (dense tiles)
 };
 
 __device__ __forceinline__ void load_tables(SharedTables &T)
@@ -436,14 +408,21 @@ __device__ __forceinline__ void scan_bins(uint32_t *bins)
     }
 }
 
+// Size key of a general vertex: 1 + lower neighbours + lower-star triangles
+// and tets (at most 75).
+__device__ __forceinline__ uint32_t size_key(uint32_t low)
+{
+    return 1u + (uint32_t)__popc(low) + (uint32_t)__popcll(lower_star_tq(low));
+}
+
 // One GX x GY x 1 tile (1024 vertices) of the owned box [lo, lo + w) of a
 // grid of dims n; record indices are rec_off + position in the owned box.
 // The orders of the tile plus a one-vertex halo are staged in LDS.  Pass 1
 // visits the tile in order (4 vertices per thread): a regular or one-defect
 // vertex takes its record from the precomputed tables; any other vertex is
-// binned by the size of its lower star.  Those are then queued (fewer than a
-// block's worth, while the queue has room) or paired here by increasing size.
-// Must be entered by the whole block.
+// listed.  A tile with fewer than kThreads listed vertices ranks them and
+// queues as many as fit (pairing any others itself); a denser tile sorts
+// them by size and pairs them itself.  Must be entered by the whole block.
 template <int GX, int GY>
 __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order, int64_t nx,
                                               int64_t ny, int64_t nz, int64_t lo0, int64_t lo1,
@@ -455,7 +434,7 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
 {
     using S = Tile<GX, GY>;
     const int tid = threadIdx.x;
-    for (int i = tid; i < kSizeBins; i += kThreads) sh.bins[i] = 0;
+    if (tid == 0) sh.nlist = 0;
     const int64_t x0 = lo0 + bx * GX - 1, y0 = lo1 + by * GY - 1, z0 = lo2 + bz - 1;
     const bool full = x0 >= 0 && y0 >= 0 && z0 >= 0 && x0 + S::HX <= nx && y0 + S::HY <= ny &&
                       z0 + S::HZ <= nz;
@@ -469,68 +448,87 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
     }
     __syncthreads();
 
-    // pass 1: table vertices; the others get a size key
+    // pass 1: table vertices; the others are listed
     const int64_t rbase = rec_off + (bx * GX) + w0 * ((by * GY) + w1 * bz);
 #pragma unroll
     for (int k = 0; k < kTileVerts / kThreads; ++k) {
         const int v = tid + k * kThreads;
         const int tx = v % GX, ty = v / GX;
-        uint32_t key = kSizeBins;  // outside the box: no work
         if (bx * GX + tx < w0 && by * GY + ty < w1 && bz < w2) {
             const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
             int32_t o[14];
             gather_orders<GX, GY>(tile, c, o);
             const uint32_t low = lower_mask(o, tile[c]);
             const uint4 *hit = table_entry(low, o, defect8);
-            if (hit) {
+            if (hit)
                 rec[rbase + tx + w0 * ty] = *hit;
-            } else {
-                key = 1 + __popc(low) + __popcll(lower_star_tq(low));
-                atomicAdd(&sh.bins[key], 1u);
-            }
+            else
+                sh.list[atomicAdd(&sh.nlist, 1u)] = (uint16_t)v;
         }
-        sh.key[v] = (uint8_t)(key < kSizeBins ? key : 0xffu);
+    }
+    __syncthreads();
+    const uint32_t total = sh.nlist;
+    if (total == 0) return;
+
+    if (queue && total < (uint32_t)kThreads) {
+        // reserve queue slots; the ranking below overlaps the atomic
+        if (tid == 0) sh.qbase = atomicAdd(qcount, total);
+        const bool mine = (uint32_t)tid < total;
+        const int v = mine ? sh.list[tid] : 0;
+        const int tx = v % GX, ty = v / GX;
+        const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
+        int32_t o[14];
+        gather_orders<GX, GY>(tile, c, o);
+        const uint32_t low = mine ? lower_mask(o, tile[c]) : 0u;
+        const uint64_t rk = mine ? lower_ranks(o, low) : 0xffffffffffffffull;
+        __syncthreads();
+        // queue as many as fit below qcap, so that every slot the queue
+        // kernel reads, [0, min(count, qcap)), has been written by this launch
+        const uint32_t qb = sh.qbase;
+        const uint32_t nq = qb >= qcap ? 0u : min(total, qcap - qb);  // uniform
+        const uint32_t ridx = (uint32_t)(rbase + tx + w0 * ty);
+        if ((uint32_t)tid < nq)
+            queue[qb + tid] = make_uint4((uint32_t)rk, (uint32_t)(rk >> 32), ridx, size_key(low));
+        if (nq == total) return;
+        // the queue is full: pair the rest here (rare, so unsorted)
+        const bool here = (uint32_t)tid >= nq && mine;
+        int mmax = here ? __popc(low) : 0;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
+        mmax = __builtin_amdgcn_readfirstlane(mmax);
+        if (here) {
+            uint4 r;
+            robins(rk, mmax, sh.T, r);
+            rec[ridx] = r;
+        }
+        return;
+    }
+
+    // a dense tile: deal its general vertices into perm by size key (the key
+    // is computed twice rather than stored: LDS is kept for occupancy)
+    for (int i = tid; i < kSizeBins; i += kThreads) sh.bins[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < total; i += kThreads) {
+        const int v = sh.list[i];
+        const int c = (v % GX + 1) + S::HX * ((v / GX + 1) + S::HY);
+        int32_t o[14];
+        gather_orders<GX, GY>(tile, c, o);
+        atomicAdd(&sh.bins[size_key(lower_mask(o, tile[c]))], 1u);
     }
     __syncthreads();
     scan_bins(sh.bins);
     __syncthreads();
-    // deal the general vertices into perm by key (within a key any order)
-#pragma unroll
-    for (int k = 0; k < kTileVerts / kThreads; ++k) {
-        const int v = tid + k * kThreads;
-        const uint32_t key = sh.key[v];
-        if (key != 0xffu) sh.perm[atomicAdd(&sh.bins[key], 1u)] = (uint16_t)v;
+    for (uint32_t i = tid; i < total; i += kThreads) {
+        const int v = sh.list[i];
+        const int c = (v % GX + 1) + S::HX * ((v / GX + 1) + S::HY);
+        int32_t o[14];
+        gather_orders<GX, GY>(tile, c, o);
+        sh.perm[atomicAdd(&sh.bins[size_key(lower_mask(o, tile[c]))], 1u)] = (uint16_t)v;
     }
     __syncthreads();
-    // the last bin is never used (keys are at most 75): its start is the total
-    const uint32_t total = sh.bins[kSizeBins - 1];
-    if (total == 0) return;
-
-    // queue the first nq (smallest) of them: as many as fit below qcap, so
-    // that every slot the queue kernel reads, [0, min(count, qcap)), has been
-    // written by this launch; the rest are paired here
-    uint32_t nq = 0;
-    if (queue && total < (uint32_t)kThreads) {
-        if (tid == 0) sh.qbase = atomicAdd(qcount, total);
-        __syncthreads();
-        const uint32_t qb = sh.qbase;
-        nq = qb >= qcap ? 0u : min(total, qcap - qb);  // uniform
-        if ((uint32_t)tid < nq) {
-            const int v = sh.perm[tid];
-            const int tx = v % GX, ty = v / GX;
-            const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
-            int32_t o[14];
-            gather_orders<GX, GY>(tile, c, o);
-            const uint32_t low = lower_mask(o, tile[c]);
-            const uint64_t rk = lower_ranks(o, low);
-            queue[qb + tid] = make_uint4((uint32_t)rk, (uint32_t)(rk >> 32),
-                                         (uint32_t)(rbase + tx + w0 * ty), sh.key[v]);
-        }
-        if (nq == total) return;
-    }
 
     // pass 2: general vertices by increasing lower-star size
-    for (uint32_t base = nq; base < total; base += kThreads) {
+    for (uint32_t base = 0; base < total; base += kThreads) {
         const uint32_t i = base + tid;
         const bool active = i < total;
         const int v = active ? sh.perm[i] : 0;
