@@ -3,12 +3,14 @@
 // neither tail nor head of a discrete vector is critical; Section 3, Extract).
 //
 // Three steps over the owned box, in box order (which is vertex-id order):
-//  count  per 256-vertex tile, the number of critical cells of each dimension,
-//         from popcounts of the record fields (no table walk);
+//  count  per 1024-record tile, the number of critical cells of each
+//         dimension, from popcounts of the record fields (no table walk),
+//         and the list of the tile's records that hold any (up to kCand);
 //  scan   an exclusive scan of the 4 x ntiles tile counts;
-//  fill   per vertex, the critical cells in (dimension, local index) order,
-//         written at tile offset + block-scan offset as int64 codes
-//         (max vertex id << 8) | local index.
+//  fill   per listed record, the critical cells in (dimension, local index)
+//         order, written at tile offset + scan offset as int64 codes
+//         (max vertex id << 8) | local index.  A tile with more than kCand
+//         such records is re-read whole.
 #include "dms_common.hpp"
 #include "dms_internal.hpp"
 #include "dms_scan.hpp"
@@ -20,6 +22,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kPerThread = 4;
 constexpr int kTileRecs = kThreads * kPerThread;  // records per block
+constexpr int kCand = 32;  // records with critical cells listed per tile
 
 struct Fields {
     uint64_t lo, hi;
@@ -179,9 +182,12 @@ __device__ __forceinline__ void load_recs(const uint4 *__restrict__ rec, int64_t
     }
 }
 
+// cand (may be null): kCand uint16 tile positions per tile, ncand: their
+// number per tile (the true number, also beyond kCand).
 __global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec, int64_t nbox,
                                                          uint64_t *__restrict__ tile_counts,
-                                                         int64_t ntiles)
+                                                         int64_t ntiles, uint16_t *__restrict__ cand,
+                                                         uint32_t *__restrict__ ncand)
 {
     __shared__ uint64_t wsum[kThreads / kWave];
     const int64_t r0 = (int64_t)blockIdx.x * kTileRecs + (int64_t)threadIdx.x * kPerThread;
@@ -199,6 +205,22 @@ __global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict
         tile_counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = lane16(t, threadIdx.x);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) tile_counts[4 * ntiles] = 0;
+    if (cand) {
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) mine += pk[k] != 0 ? 1u : 0u;
+        uint32_t tot;
+        uint32_t a = block_exclusive_scan<uint32_t>(mine, &tot);
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            if (pk[k] != 0) {
+                if (a < (uint32_t)kCand)
+                    cand[(int64_t)blockIdx.x * kCand + a] = (uint16_t)(threadIdx.x * kPerThread + k);
+                ++a;
+            }
+        }
+        if (threadIdx.x == 0) ncand[blockIdx.x] = tot;
+    }
 }
 
 // Shared by the single-field and batched fill: records [r0, r0 + 4) of
@@ -220,7 +242,8 @@ __device__ __forceinline__ void fill_slots(const uint64_t *pk, const uint64_t *_
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_crit_fill(
+// All records of one tile (the whole block).
+__device__ __forceinline__ void fill_tile_full(
     const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
     int64_t w0, int64_t w1, int64_t lo0, int64_t lo1, int64_t lo2, int64_t nx, int64_t ny,
     int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
@@ -239,6 +262,58 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill(
         const int64_t v = box_vertex(r0 + k, w0, w1, lo0, lo1, lo2, nx, ny);
         write_codes(lo[k], hi[k], c, at[k], v << 8, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
     }
+}
+
+// Fill from the candidate lists: a tile with at most kCand listed records
+// reads only those (one wave; their slots from a wave scan of the packed
+// counts), a tile with more is re-read whole, a tile with none is skipped.
+__global__ __launch_bounds__(kThreads) void k_crit_fill(
+    const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
+    const uint16_t *__restrict__ cand, const uint32_t *__restrict__ ncand, int64_t w0, int64_t w1,
+    int64_t lo0, int64_t lo1, int64_t lo2, int64_t nx, int64_t ny, int64_t *crit0, int64_t *crit1,
+    int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
+{
+    const uint32_t n = ncand[blockIdx.x];
+    if (n == 0) return;  // uniform
+    if (n > (uint32_t)kCand) {
+        fill_tile_full(rec, nbox, offs, ntiles, w0, w1, lo0, lo1, lo2, nx, ny, crit0, crit1, crit2,
+                       crit3, cap0, cap1, cap2, cap3);
+        return;
+    }
+    if (threadIdx.x >= kWave) return;
+    const int lane = threadIdx.x;
+    const bool active = (uint32_t)lane < n;
+    uint64_t lo = 0, hi = 0, pk = 0;
+    int64_t r = 0;
+    if (active) {
+        r = (int64_t)blockIdx.x * kTileRecs + cand[(int64_t)blockIdx.x * kCand + lane];
+        if (r < nbox) {
+            const uint4 w = rec[r];
+            lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
+            hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
+            uint32_t c[4];
+            count_critical(lo, hi, c);
+            pk = pack4(c);
+        }
+    }
+    // exclusive scan of the packed counts over the wave
+    uint64_t inc = pk;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    const uint64_t ex = inc - pk;
+    if (pk == 0) return;
+    uint64_t at[4];
+    uint32_t c[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        at[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles] + lane16(ex, d);
+        c[d] = lane16(pk, d);
+    }
+    const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
+    write_codes(lo, hi, c, at, v << 8, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 }
 
 __global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *counts, int64_t cap0,
@@ -340,7 +415,7 @@ int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, i
     uint64_t *tc = (uint64_t *)ws;
     uint64_t *partials = (uint64_t *)(ws + align_up((size_t)len * 8, 256));
     hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       n, tc, ntiles);
+                       n, tc, ntiles, nullptr, nullptr);
     exclusive_scan<uint64_t>(tc, len, partials, s);
     hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
                        (const uint4 *)rec, n, tc, ntiles, foff, nfields, offsets, crit[0], crit[1],
@@ -352,15 +427,33 @@ int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, i
 
 }  // namespace dms
 
+namespace {
+// Single-field workspace: tile counts (4 x ntiles + 1, scanned in place),
+// scan partials, candidate positions (kCand per tile), candidate counts.
+struct CritLayout {
+    size_t partials, cand, ncand, total;
+};
+
+CritLayout crit_layout(int64_t ntiles)
+{
+    const int64_t len = 4 * ntiles + 1;
+    CritLayout L{};
+    size_t off = dms::align_up((size_t)len * 8, 256);
+    L.partials = off; off += dms::scan_partials_bytes(len, 8);
+    L.cand = off; off += dms::align_up((size_t)ntiles * dms::kCand * 2, 256);
+    L.ncand = off; off += dms::align_up((size_t)ntiles * 4, 256);
+    L.total = off;
+    return L;
+}
+}  // namespace
+
 extern "C" size_t dms_critical_workspace_size(const int64_t dims[3], const int64_t lo[3],
                                               const int64_t hi[3])
 {
     using namespace dms;
     if (!box_valid(dims, lo, hi)) return 0;
     const int64_t nbox = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
-    const int64_t ntiles = (nbox + kTileRecs - 1) / kTileRecs;
-    const int64_t len = 4 * ntiles + 1;
-    return align_up((size_t)len * 8, 256) + scan_partials_bytes(len, 8);
+    return crit_layout((nbox + kTileRecs - 1) / kTileRecs).total;
 }
 
 extern "C" int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3], const int64_t lo[3],
@@ -384,18 +477,21 @@ extern "C" int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3]
     hipStream_t s = (hipStream_t)stream;
     const int64_t ntiles = (nbox + kTileRecs - 1) / kTileRecs;
     const int64_t len = 4 * ntiles + 1;
+    const CritLayout L = crit_layout(ntiles);
     uint64_t *tc = (uint64_t *)workspace;
-    uint64_t *partials = (uint64_t *)((char *)workspace + align_up((size_t)len * 8, 256));
+    uint64_t *partials = (uint64_t *)((char *)workspace + L.partials);
+    uint16_t *cand = (uint16_t *)((char *)workspace + L.cand);
+    uint32_t *ncand = (uint32_t *)((char *)workspace + L.ncand);
     if (ntiles == 0) {
         hipLaunchKernelGGL(k_crit_empty, dim3(1), dim3(64), 0, s, counts);
         return launch_status();
     }
     hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       nbox, tc, ntiles);
+                       nbox, tc, ntiles, cand, ncand);
     exclusive_scan<uint64_t>(tc, len, partials, s);
     hipLaunchKernelGGL(k_crit_fill, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                           nbox, tc, ntiles, w0, w1, lo[0], lo[1], lo[2], dims[0], dims[1], crit0,
-                           crit1, crit2, crit3, cap[0], cap[1], cap[2], cap[3]);
+                       nbox, tc, ntiles, cand, ncand, w0, w1, lo[0], lo[1], lo[2], dims[0], dims[1],
+                       crit0, crit1, crit2, crit3, cap[0], cap[1], cap[2], cap[3]);
     hipLaunchKernelGGL(k_crit_finish, dim3(1), dim3(64), 0, s, tc, ntiles, counts, cap[0], cap[1],
                        cap[2], cap[3], dev_flags);
     return launch_status();

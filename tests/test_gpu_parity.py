@@ -45,6 +45,10 @@ def _field(dims, kind, seed):
         return inputs.mixture_field((nz, ny, nx), 6, rng, 1e-3, np.float32)
     if kind == "f64":
         return inputs.mixture_field((nz, ny, nx), 6, rng, 1e-4, np.float64)
+    if kind.startswith("ramp"):  # tilted ramp + uniform noise of the given amplitude
+        k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        amp = float(kind[4:])
+        return (i + 1.37 * j + 1.91 * k + amp * rng.random((nz, ny, nx))).astype(np.float32)
     raise ValueError(kind)
 
 
@@ -219,6 +223,11 @@ def test_gradient_hand_worked_cube():
     ((34, 34, 34), "noise", 4, ((1, 1, 1), (33, 33, 33))),
     ((3, 3, 3), "noise", 5, None),
     ((7, 1, 1), "noise", 6, None),
+    # extraction tiles with few, about kCand and many records holding
+    # critical cells (listed, listed up to the limit, re-read whole)
+    ((128, 64, 24), "ramp1.2", 7, None),
+    ((128, 64, 24), "ramp4.0", 8, None),
+    ((128, 64, 24), "ramp6.0", 9, ((1, 1, 1), (127, 63, 23))),
 ])
 def test_critical_lists(dims, kind, seed, box):
     v = _field(dims, kind, seed)
