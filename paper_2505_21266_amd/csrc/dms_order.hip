@@ -57,9 +57,18 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t ntiles)
     return (b % 8) * per + b / 8;
 }
 
-__device__ __forceinline__ int64_t elem_index(int64_t tile, int wave, int k, int lane)
+
+// Element k of this lane in its tile (wave-striped), as an offset from the
+// tile's first element.
+__device__ __forceinline__ int local_index(int wave, int k, int lane)
 {
-    return tile * kTile + (int64_t)wave * (kItems * kWave) + k * kWave + lane;
+    return wave * (kItems * kWave) + k * kWave + lane;
+}
+
+__device__ __forceinline__ int tile_count(int64_t n, int64_t tile)
+{
+    const int64_t left = n - tile * kTile;
+    return left <= 0 ? 0 : (left < kTile ? (int)left : kTile);
 }
 
 // Histogram update for one item per lane (counts only, no ranks): an LDS
@@ -108,25 +117,27 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t
     }
     __syncthreads();
     const int64_t tile = tile_of_block(ntiles);
+    const int64_t t0 = tile * kTile;
+    const int count = tile_count(n, tile);
     bool nan_any = false;
     uint32_t dig[kItems];
     if (ids) {
         uint32_t bk[kItems];
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
-            const int64_t i = elem_index(tile, wave, k, lane);
-            bk[k] = i < n ? (ids[i] >> bshift) & (kRadix - 1) : (uint32_t)kRadix;
+            const int li = local_index(wave, k, lane);
+            bk[k] = li < count ? (ids[t0 + li] >> bshift) & (kRadix - 1) : (uint32_t)kRadix;
         }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) hist_add(bhist[wave], bk[k], bk[k] < (uint32_t)kRadix);
     }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {  // all loads first
-        const int64_t i = elem_index(tile, wave, k, lane);
+        const int li = local_index(wave, k, lane);
         dig[k] = kRadix;
-        if (i < n) {
+        if (li < count) {
             bool nan;
-            K key = load_key<V, K, kFirst>(src, i, nan);
+            K key = load_key<V, K, kFirst>(src, t0 + li, nan);
             nan_any |= nan;
             dig[k] = (uint32_t)(key >> shift) & (kRadix - 1);
         }
@@ -150,9 +161,28 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t
 // Rank of an item among the wave's items with the same 8-bit digit, counting
 // this k and all earlier ones; wh is the wave's row of counts.  Items of a
 // wave are in element order (k major, lane minor), so ranks are stable.
-__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t *wh)
+// The lanes holding the same digit are found either by eight ballots
+// (kLds false) or through LDS (kLds true): each lane ORs its lane bit into
+// the wave's mask slot of its digit (mk, zero between uses), reads the slot
+// back and clears it -- three LDS operations in place of some forty vector
+// instructions, which pays where the vector units are the busier resource
+// (measured per pass).  A wave whose lanes share one digit (the high bytes of
+// a smooth field) skips either.
+template <bool kLds>
+__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t *wh, uint64_t *mk)
 {
-    const uint64_t peers = match_digit8(d, __ballot(valid));
+    const uint64_t act = __ballot(valid);
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(valid ? d : 0xffffffffu);
+    uint64_t peers;
+    if (__ballot(valid && d == d0) == act) {
+        peers = act;
+    } else if constexpr (kLds) {
+        if (valid) atomicOr((unsigned long long *)&mk[d], 1ull << lane_id());
+        peers = valid ? mk[d] : 0ull;
+        if (valid) mk[d] = 0ull;
+    } else {
+        peers = match_digit8(d, act);
+    }
     uint32_t base = 0;
     if (valid) base = wh[d];
     const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
@@ -180,6 +210,23 @@ __device__ __forceinline__ uint32_t wave_prefix(uint32_t (*wh)[kRadix])
 // scanned counts (global start of digit d in tile `tile`).
 // foff (nfields + 1 offsets) is non-null for batches: the first pass puts
 // the field index above the value key.
+// LDS staging of a tile; the digit masks of the ranking phase live in the
+// same bytes (the phases are separated by a barrier).
+template <typename A, typename B>
+union Staging {
+    struct {
+        A a[kTile];
+        B b[kTile];
+    } st;
+    uint64_t mk[kWaves][kRadix];
+};
+
+template <typename A, typename B>
+__device__ __forceinline__ void zero_masks(Staging<A, B> &S)
+{
+    for (int i = threadIdx.x; i < kWaves * kRadix; i += kThreads) (&S.mk[0][0])[i] = 0ull;
+}
+
 template <typename V, typename K, bool kFirst>
 __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uint32_t *src_ids,
                                                       int64_t n, int shift,
@@ -190,64 +237,67 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
     __shared__ uint32_t whist[kWaves][kRadix];
     __shared__ uint32_t digit_start[kRadix];
     __shared__ uint32_t gbase[kRadix];
-    __shared__ K skey[kTile];
-    __shared__ uint32_t sid[kTile];
+    __shared__ Staging<K, uint32_t> S;
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     for (int i = tid; i < kWaves * kRadix; i += kThreads) (&whist[0][0])[i] = 0;
+    zero_masks(S);
     __syncthreads();
 
     const int64_t tile = tile_of_block(ntiles);
+    const int64_t t0 = tile * kTile;
+    const int count = tile_count(n, tile);
     K key[kItems];
     uint32_t id[kItems];
     uint32_t rank[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        const int64_t i = elem_index(tile, wave, k, lane);
-        const bool valid = i < n;
+        const int li = local_index(wave, k, lane);
         key[k] = 0;
         id[k] = 0;
-        if (valid) {
+        if (li < count) {
             bool nan;
-            key[k] = load_key<V, K, kFirst>(src, i, nan);
+            key[k] = load_key<V, K, kFirst>(src, t0 + li, nan);
             if constexpr (kFirst && sizeof(K) == 8) {
-                if (foff) key[k] |= (K)field_of(foff, nfields, i) << 32;
+                if (foff) key[k] |= (K)field_of(foff, nfields, t0 + li) << 32;
             }
-            id[k] = kFirst ? (uint32_t)i : src_ids[i];
+            id[k] = kFirst ? (uint32_t)(t0 + li) : src_ids[t0 + li];
         }
-        rank[k] = wave_rank((uint32_t)(key[k] >> shift) & (kRadix - 1), valid, whist[wave]);
     }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+        rank[k] = wave_rank<!kFirst>((uint32_t)(key[k] >> shift) & (kRadix - 1),
+                                     local_index(wave, k, lane) < count, whist[wave], S.mk[wave]);
     __syncthreads();
     {
         uint32_t total;
-        digit_start[tid] = block_exclusive_scan<uint32_t>(wave_prefix(whist), &total);
-        gbase[tid] = offsets[(int64_t)tid * ntiles + tile];
+        const uint32_t start = block_exclusive_scan<uint32_t>(wave_prefix(whist), &total);
+        digit_start[tid] = start;
+        // global position of the tile's element at local position p of digit d:
+        // gbase[d] + p (gbase holds the scanned offset minus the local start)
+        gbase[tid] = offsets[(int64_t)tid * ntiles + tile] - start;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        const int64_t i = elem_index(tile, wave, k, lane);
-        if (i < n) {
+        if (local_index(wave, k, lane) < count) {
             const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
             const uint32_t pos = digit_start[d] + whist[wave][d] + rank[k];
-            skey[pos] = key[k];
-            sid[pos] = id[k];
+            S.st.a[pos] = key[k];
+            S.st.b[pos] = id[k];
         }
     }
     __syncthreads();
-    const int64_t left = n - tile * kTile;
-    const int count = left < kTile ? (int)left : kTile;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int p = tid + j * kThreads;
         if (p < count) {
-            const K kk = skey[p];
-            const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
-            const uint32_t g = gbase[d] + (uint32_t)(p - (int)digit_start[d]);
+            const K kk = S.st.a[p];
+            const uint32_t g = gbase[(uint32_t)(kk >> shift) & (kRadix - 1)] + (uint32_t)p;
             // the ranks make g < n; the guard keeps any breach of that in bounds
             if ((int64_t)g < n) {
                 dst_keys[g] = kk;
-                dst_ids[g] = sid[p];
+                dst_ids[g] = S.st.b[p];
             }
         }
     }
@@ -319,17 +369,19 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t bstart[kRadix];
     __shared__ uint32_t bbase[kRadix];
-    __shared__ uint32_t sid[kTile];
-    __shared__ int32_t spos[kTile];
+    __shared__ Staging<uint32_t, int32_t> S;
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     for (int i = tid; i < kWaves * kRadix; i += kThreads) {
         (&dwh[0][0])[i] = 0;
         (&bwh[0][0])[i] = 0;
     }
+    zero_masks(S);
     __syncthreads();
 
     const int64_t tile = tile_of_block(ntiles);
+    const int64_t t0 = tile * kTile;
+    const int count = tile_count(n, tile);
     // per item after the ranking: id, (digit rank | digit << 16) and
     // (bucket rank | field << 16); ranks are below kTile = 2^12
     uint32_t id[kItems], dr[kItems], br[kItems];
@@ -337,33 +389,34 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
         K key[kItems];
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
-            const int64_t i = elem_index(tile, wave, k, lane);
-            const bool valid = i < n;
-            key[k] = valid ? src[i] : K(0);
-            id[k] = valid ? src_ids[i] : 0u;
+            const int li = local_index(wave, k, lane);
+            const bool valid = li < count;
+            key[k] = valid ? src[t0 + li] : K(0);
+            id[k] = valid ? src_ids[t0 + li] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
-            const bool valid = elem_index(tile, wave, k, lane) < n;
+            const bool valid = local_index(wave, k, lane) < count;
             const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-            dr[k] = wave_rank(d, valid, dwh[wave]) | d << 16;
+            dr[k] = wave_rank<true>(d, valid, dwh[wave], S.mk[wave]) | d << 16;
             uint32_t field = 0;
             if constexpr (sizeof(K) == 8) field = (uint32_t)(key[k] >> 32);
-            br[k] = wave_rank((id[k] >> bshift) & (kRadix - 1), valid, bwh[wave]) | field << 16;
+            br[k] = wave_rank<true>((id[k] >> bshift) & (kRadix - 1), valid, bwh[wave], S.mk[wave]) | field << 16;
         }
     }
     __syncthreads();
     {
         wave_prefix(dwh);
         uint32_t total;
-        bstart[tid] = block_exclusive_scan<uint32_t>(wave_prefix(bwh), &total);
+        const uint32_t start = block_exclusive_scan<uint32_t>(wave_prefix(bwh), &total);
+        bstart[tid] = start;
         gbase[tid] = offsets[(int64_t)tid * ntiles + tile];
-        bbase[tid] = boffsets[(int64_t)tid * ntiles + tile];
+        bbase[tid] = boffsets[(int64_t)tid * ntiles + tile] - start;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        if (elem_index(tile, wave, k, lane) < n) {
+        if (local_index(wave, k, lane) < count) {
             const uint32_t d = dr[k] >> 16;
             const uint32_t b = (id[k] >> bshift) & (kRadix - 1);
             const int64_t g = (int64_t)gbase[d] + dwh[wave][d] + (dr[k] & 0xffffu);
@@ -373,24 +426,21 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
             }
             const uint32_t pos = bstart[b] + bwh[wave][b] + (br[k] & 0xffffu);
             if (pos < (uint32_t)kTile) {
-                sid[pos] = id[k];
-                spos[pos] = (int32_t)(g - base);
+                S.st.a[pos] = id[k];
+                S.st.b[pos] = (int32_t)(g - base);
             }
         }
     }
     __syncthreads();
-    const int64_t left = n - tile * kTile;
-    const int count = left < kTile ? (int)left : kTile;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int p = tid + j * kThreads;
         if (p < count) {
-            const uint32_t who = sid[p];
-            const uint32_t b = (who >> bshift) & (kRadix - 1);
-            const int64_t dst = (int64_t)bbase[b] + (p - (int)bstart[b]);
-            if (dst < n) {
+            const uint32_t who = S.st.a[p];
+            const uint32_t dst = bbase[(who >> bshift) & (kRadix - 1)] + (uint32_t)p;
+            if ((int64_t)dst < n) {
                 pair_id[dst] = who;
-                pair_pos[dst] = spos[p];
+                pair_pos[dst] = S.st.b[p];
             }
         }
     }
@@ -414,12 +464,14 @@ __global__ __launch_bounds__(kThreads) void k_fine_hist(const uint32_t *pair_id,
     for (int i = tid; i < kWaves * kRadix; i += kThreads) (&hist[0][0])[i] = 0;
     __syncthreads();
     const int64_t c = tile_of_block(nchunks);
+    const int64_t t0 = c * kTile;
+    const int count = tile_count(n, c);
     const uint32_t fmask = (1u << flog) - 1u;
     uint32_t dig[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        const int64_t i = elem_index(c, wave, k, lane);
-        dig[k] = i < n ? (pair_id[i] >> fshift) & fmask : (uint32_t)kRadix;
+        const int li = local_index(wave, k, lane);
+        dig[k] = li < count ? (pair_id[t0 + li] >> fshift) & fmask : (uint32_t)kRadix;
     }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) hist_add(hist[wave], dig[k], dig[k] < (uint32_t)kRadix);
@@ -440,59 +492,58 @@ __global__ __launch_bounds__(kThreads) void k_fine_scatter(const uint32_t *in_id
     __shared__ uint32_t wh[kWaves][kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
-    __shared__ uint32_t sid[kTile];
-    __shared__ int32_t spos[kTile];
+    __shared__ Staging<uint32_t, int32_t> S;
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     for (int i = tid; i < kWaves * kRadix; i += kThreads) (&wh[0][0])[i] = 0;
+    zero_masks(S);
     __syncthreads();
     const int64_t c = tile_of_block(nchunks);
+    const int64_t t0 = c * kTile;
+    const int count = tile_count(n, c);
     const uint32_t fmask = (1u << flog) - 1u;
     uint32_t id[kItems], r[kItems];
     int32_t pos[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        const int64_t i = elem_index(c, wave, k, lane);
-        const bool valid = i < n;
-        id[k] = valid ? in_id[i] : 0u;
-        pos[k] = valid ? in_pos[i] : 0;
+        const int li = local_index(wave, k, lane);
+        const bool valid = li < count;
+        id[k] = valid ? in_id[t0 + li] : 0u;
+        pos[k] = valid ? in_pos[t0 + li] : 0;
     }
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const bool valid = elem_index(c, wave, k, lane) < n;
-        r[k] = wave_rank((id[k] >> fshift) & fmask, valid, wh[wave]);
-    }
+    for (int k = 0; k < kItems; ++k)
+        r[k] = wave_rank<false>((id[k] >> fshift) & fmask, local_index(wave, k, lane) < count, wh[wave],
+                               S.mk[wave]);
     __syncthreads();
     {
         uint32_t total;
-        dstart[tid] = block_exclusive_scan<uint32_t>(wave_prefix(wh), &total);
-        gbase[tid] = tid <= (int)fmask ? offsets[fine_count_index(c, tid, flog, qlog)] : 0u;
+        const uint32_t start = block_exclusive_scan<uint32_t>(wave_prefix(wh), &total);
+        dstart[tid] = start;
+        gbase[tid] = (tid <= (int)fmask ? offsets[fine_count_index(c, tid, flog, qlog)] : 0u) - start;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-        if (elem_index(c, wave, k, lane) < n) {
+        if (local_index(wave, k, lane) < count) {
             const uint32_t d = (id[k] >> fshift) & fmask;
             const uint32_t at = dstart[d] + wh[wave][d] + r[k];
             if (at < (uint32_t)kTile) {
-                sid[at] = id[k];
-                spos[at] = pos[k];
+                S.st.a[at] = id[k];
+                S.st.b[at] = pos[k];
             }
         }
     }
     __syncthreads();
-    const int64_t left = n - c * kTile;
-    const int count = left <= 0 ? 0 : (left < kTile ? (int)left : kTile);
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int p = tid + j * kThreads;
         if (p < count) {
-            const uint32_t who = sid[p];
-            const uint32_t d = (who >> fshift) & fmask;
-            const int64_t dst = (int64_t)gbase[d] + (p - (int)dstart[d]);
-            if (dst < n) {
+            const uint32_t who = S.st.a[p];
+            const uint32_t dst = gbase[(who >> fshift) & fmask] + (uint32_t)p;
+            if ((int64_t)dst < n) {
                 out_id[dst] = who;
-                out_pos[dst] = spos[p];
+                out_pos[dst] = S.st.b[p];
             }
         }
     }
