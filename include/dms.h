@@ -18,9 +18,10 @@
  *    `stream` (a hipStream_t, NULL = the default stream) and return.  One
  *    exception: the first dms_discrete_gradient (or dms_batch_create) on a
  *    device fills constant device tables of lower-star records -- 10 MB for
- *    the stars whose lower neighbours are one of each opposite pair, 5 MB
- *    and 289 MB (allocated there, kept until the process ends) for those
- *    with one pair wholly upper or wholly lower -- and waits for them once.
+ *    the stars whose lower neighbours are one of each opposite pair, 36 MB
+ *    and 289 MB (the latter allocated there, kept until the process ends)
+ *    for those with one pair wholly upper or wholly lower -- and waits for
+ *    them once.
  *  - Argument errors are returned synchronously as a dms_status and nothing
  *    is enqueued.  Data-dependent conditions found on the device are OR-ed
  *    into *dev_flags (a device uint32 the caller zeroes), read after a sync.

@@ -284,28 +284,31 @@ constexpr int kRegular = 128 * kPerm7;
 __device__ uint4 g_regular[kRegular];
 
 // One-defect vertices: six pairs have one lower member and the seventh has
-// both (8 lower neighbours) or neither (6).  The records of these two
-// families are tabulated the same way, by defect pair j, the sides of the
-// other six pairs and the order of the lower neighbours:
-//   |L| = 8: index ((j * 64 + side6) * 8! + code8) -- 289 MB, allocated once
-//            per device; the order is that of v[i] = lower member of pair i
-//            (neighbour 13 - i for i = j) for i < 7, then v[7] = neighbour j;
-//   |L| = 6: index ((j * 64 + side6) * 6! + code6), the order of the lower
-//            members of the pairs other than j, in pair order.
+// both (8 lower neighbours) or neither (6).  All three families are looked
+// up from one set of eight slots: v[i] = the member of pair i on the lower
+// side (neighbour 13 - i when side bit i is set, else i) for i < 7, and
+// v[7] = the smallest order among the other members -- neighbour j itself
+// when pair j is wholly lower, else an upper order (replaced by a value
+// above every order).  The Lehmer digits l_i count the later slots holding
+// smaller orders; the codes are fixed-radix factorial sums of them:
+//   code7 = sum over i < 7 of l_i (6 - i)!   (regular and |L| = 6)
+//   code8 = sum over i < 8 of l_i (7 - i)!   (|L| = 8)
+// For |L| = 6 slot j holds an upper order, larger than every lower one, so
+// its digit is always 6 - j: the code is injective but sparse (one code in
+// seven is used), which keeps the lookup free of any per-lane dependence on
+// j beyond the table offset.
+//   regular: index side * 7! + code7                       (10 MB)
+//   |L| = 6: index (j * 64 + side6) * 7! + code7            (36 MB, sparse)
+//   |L| = 8: index (j * 64 + side6) * 8! + code8            (289 MB, allocated
+//            once per device)
 // side6 is the 7-bit side pattern with bit j removed.
-constexpr int kPerm6 = 720;
 constexpr int kPerm8 = 40320;
-constexpr int kDefect6 = 7 * 64 * kPerm6;
+constexpr int kDefect6 = 7 * 64 * kPerm7;
 constexpr int64_t kDefect8 = 7ll * 64 * kPerm8;
 __device__ uint4 g_defect6[kDefect6];
 
 // Record of x from one of the tables, or null when x is in none of the
 // families (defect8 may be null: that family then takes the general path).
-// One Lehmer computation serves the three families: eight slots v[i] (the
-// lower member of pair i for i < 7, then neighbour j), with a sentinel above
-// every order in the slots a family does not use, so that each digit l_i
-// counts only used slots; the families differ only in the radix of each
-// digit (Horner form of the factorial-base code).
 __device__ __forceinline__ const uint4 *table_entry(uint32_t low, const int32_t *o,
                                                     const uint4 *__restrict__ defect8)
 {
@@ -314,36 +317,44 @@ __device__ __forceinline__ const uint4 *table_entry(uint32_t low, const int32_t 
     const uint32_t one = (low ^ rev) & 0x7fu;
     const int npair = __popc(one);
     if (npair < 6) return nullptr;
-    const bool regular = npair == 7;
-    uint32_t side = __brev((low >> 7) & 0x7fu) >> 25;  // bit i: the lower member is 13 - i
-    const uint32_t j = regular ? 7u : (uint32_t)__ffs(~one & 0x7fu) - 1u;
-    const bool eight = !regular && ((low >> j) & 1u);  // pair j wholly lower
-    if (eight && !defect8) return nullptr;
-    const bool six = !regular && !eight;               // pair j wholly upper
+    const uint32_t side = __brev((low >> 7) & 0x7fu) >> 25;  // bit i: the lower member is 13 - i
+    const uint32_t both = low & rev & 0x7fu;                   // pairs wholly lower
+    // slot values without selecting between array elements by a per-lane
+    // index (which the compiler expands into chains of compares): the lower
+    // member of a single pair is the smaller order of the two; a wholly lower
+    // pair (side bit set) takes neighbour 13 - i, and neighbour i goes to
+    // slot 7
     int32_t v[8];
-    int32_t oj = kHigh;
+    int32_t v7 = kHigh;
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
-        const int32_t lowm = ((side >> i) & 1u) ? o[13 - i] : o[i];
-        v[i] = six && (uint32_t)i == j ? kHigh : lowm;
-        oj = (uint32_t)i == j ? o[i] : oj;
+        const int32_t a = o[i], b = o[13 - i];
+        const bool w = (both >> i) & 1u;
+        v[i] = w ? b : min(a, b);
+        v7 = min(v7, w ? a : kHigh);
     }
-    v[7] = eight ? oj : kHigh;
-    uint32_t code = 0;
+    const bool eight = both != 0;
+    if (eight && !defect8) return nullptr;
+    v[7] = v7;
+    uint32_t l[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        uint32_t l = 0;
+        l[i] = 0;
 #pragma unroll
-        for (int k = i + 1; k < 8; ++k) l += v[k] < v[i] ? 1u : 0u;
-        // radix of digit i: the number of used slots from i on
-        const uint32_t radix = eight ? 8u - i : (six && (uint32_t)i > j ? 7u - i : 7u - i - (six ? 1u : 0u));
-        const bool used = eight || (i < 7 && !(six && (uint32_t)i == j));
-        code = used ? code * radix + l : code;
+        for (int k = i + 1; k < 8; ++k) l[i] += v[k] < v[i] ? 1u : 0u;
     }
-    if (regular) return &g_regular[side * kPerm7 + code];
+    constexpr uint32_t f7[7] = {720, 120, 24, 6, 2, 1, 1};
+    constexpr uint32_t f8[8] = {5040, 720, 120, 24, 6, 2, 1, 1};
+    uint32_t code7 = 0, code8 = 0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) code7 += l[i] * f7[i];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) code8 += l[i] * f8[i];
+    if (npair == 7) return &g_regular[side * kPerm7 + code7];
+    const uint32_t j = (uint32_t)__ffs(~one & 0x7fu) - 1u;
     const uint32_t side6 = (side & ((1u << j) - 1u)) | ((side >> (j + 1u)) << j);
-    if (eight) return defect8 + ((int64_t)(j * 64u + side6) * kPerm8 + code);
-    return &g_defect6[(j * 64u + side6) * kPerm6 + code];
+    if (eight) return defect8 + ((int64_t)(j * 64u + side6) * kPerm8 + code8);
+    return &g_defect6[(j * 64u + side6) * kPerm7 + code7];
 }
 
 template <int GX, int GY>
@@ -697,16 +708,18 @@ __global__ __launch_bounds__(kThreads) void k_regular_table()
     g_regular[idx] = r;
 }
 
-// Fills a one-defect table (8 lower neighbours when eight, else 6), in the
-// layout table_entry reads.
+// Fills a one-defect table in the layout table_entry reads: for |L| = 8 the
+// code is that of 8 slots (slot 7 = neighbour j); for |L| = 6 that of 7
+// slots where slot j (pair j, wholly upper) ranks above the other six --
+// entries whose code puts it elsewhere are never read and stay zero.
 template <bool kEight>
 __global__ __launch_bounds__(kThreads) void k_defect_table(uint4 *table)
 {
     __shared__ SharedTables T;
     load_tables(T);
     __syncthreads();
-    constexpr int N = kEight ? 8 : 6;
-    constexpr int64_t perms = kEight ? kPerm8 : kPerm6;
+    constexpr int N = kEight ? 8 : 7;
+    constexpr int64_t perms = kEight ? kPerm8 : kPerm7;
     const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= 7 * 64 * perms) return;
     const uint32_t code = (uint32_t)(idx % perms);
@@ -717,12 +730,15 @@ __global__ __launch_bounds__(kThreads) void k_defect_table(uint4 *table)
                           (kEight ? 1u << j : 0u);
     uint32_t rank[N];
     lehmer_decode<N>(code, rank);
+    if (!kEight && rank[j] != 6u) {
+        table[idx] = make_uint4(0, 0, 0, 0);
+        return;
+    }
     int32_t o[14];
     for (int e = 0; e < 14; ++e) o[e] = 100 + e;  // above x unless set below
-    int p = 0;
     for (int i = 0; i < 7; ++i) {
         if (!kEight && (uint32_t)i == j) continue;
-        o[((side >> i) & 1u) ? 13 - i : i] = (int32_t)rank[p++];
+        o[((side >> i) & 1u) ? 13 - i : i] = (int32_t)rank[i];
     }
     if (kEight) o[j] = (int32_t)rank[7];
     uint4 r;
