@@ -449,13 +449,27 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
     const int64_t x0 = lo0 + bx * GX - 1, y0 = lo1 + by * GY - 1, z0 = lo2 + bz - 1;
     const bool full = x0 >= 0 && y0 >= 0 && z0 >= 0 && x0 + S::HX <= nx && y0 + S::HY <= ny &&
                       z0 + S::HZ <= nz;
-    for (int i = tid; i < S::kHalo; i += kThreads) {
-        const int hx = i % S::HX, hy = (i / S::HX) % S::HY, hz = i / (S::HX * S::HY);
-        const int64_t x = x0 + hx, y = y0 + hy, z = z0 + hz;
-        int32_t v = kAbsent;
-        if (full || (x >= 0 && y >= 0 && z >= 0 && x < nx && y < ny && z < nz))
-            v = order[x + nx * (y + ny * z)];
-        tile[i] = v;
+    if (full && nx * S::HY < (1ll << 31)) {
+        // inside the grid: a plane pointer per halo plane (uniform) and a
+        // 32-bit offset within the plane
+        constexpr int kPlane = S::HX * S::HY;
+        const int nxi = (int)nx;
+#pragma unroll
+        for (int hz = 0; hz < S::HZ; ++hz) {
+            const int32_t *src = order + (x0 + nx * (y0 + ny * (z0 + hz)));
+            for (int i = tid; i < kPlane; i += kThreads) {
+                const int hy = i / S::HX, hx = i - hy * S::HX;
+                tile[hz * kPlane + i] = src[hx + hy * nxi];
+            }
+        }
+    } else {
+        for (int i = tid; i < S::kHalo; i += kThreads) {
+            const int hx = i % S::HX, hy = (i / S::HX) % S::HY, hz = i / (S::HX * S::HY);
+            const int64_t x = x0 + hx, y = y0 + hy, z = z0 + hz;
+            int32_t v = kAbsent;
+            if (x >= 0 && y >= 0 && z >= 0 && x < nx && y < ny && z < nz) v = order[x + nx * (y + ny * z)];
+            tile[i] = v;
+        }
     }
     __syncthreads();
 
