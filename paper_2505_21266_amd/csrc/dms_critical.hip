@@ -68,6 +68,47 @@ __device__ __forceinline__ uint32_t lower_tets(uint32_t low)
     return ~out & ((1u << 24) - 1);
 }
 
+// Number of star triangles (low byte) and tets (high byte) in L(x) for each
+// 14-bit lower-neighbour mask: the cells all of whose other vertices are
+// lower neighbours.
+struct CellCounts {
+    uint16_t n[1 << 14];
+};
+
+// Built incrementally: adding the highest lower neighbour e to a mask adds
+// the triangles {e, a} with a lower (a in the link of e) and the tets {e, a,
+// b} with a and b lower.
+constexpr CellCounts make_cell_counts()
+{
+    CellCounts C{};
+    const Tables &T = kTables;
+    uint16_t tet_pairs[14][24] = {};
+    int npairs[14] = {};
+    for (int q = 0; q < 24; ++q)
+        for (int c = 0; c < 3; ++c) {
+            const int e = T.tet[q][c];
+            uint16_t m = 0;
+            for (int d = 0; d < 3; ++d)
+                if (d != c) m = (uint16_t)(m | (1u << T.tet[q][d]));
+            tet_pairs[e][npairs[e]++] = m;
+        }
+    C.n[0] = 0;
+    for (uint32_t low = 1; low < (1u << 14); ++low) {
+        int e = 13;
+        while (!((low >> e) & 1u)) --e;
+        const uint32_t rest = low & ~(1u << e);
+        uint32_t nt = 0, nq = 0;
+        for (uint32_t m = T.link[e] & rest; m; m &= m - 1) ++nt;
+        for (int k = 0; k < npairs[e]; ++k)
+            if ((tet_pairs[e][k] & rest) == tet_pairs[e][k]) ++nq;
+        const uint32_t prev = C.n[rest];
+        C.n[low] = (uint16_t)(((prev & 0xffu) + nt) | (((prev >> 8) + nq) << 8));
+    }
+    return C;
+}
+
+__device__ const CellCounts g_cell_counts = make_cell_counts();
+
 constexpr uint64_t kNib14 = 0x00ffffffffffffffull;  // 14 nibbles
 
 __device__ __forceinline__ void count_critical(uint64_t lo, uint64_t hi, uint32_t c[4])
@@ -86,8 +127,9 @@ __device__ __forceinline__ void count_critical(uint64_t lo, uint64_t hi, uint32_
                              (uint32_t)__popcll((t1 | (t1 >> 1)) & 0x5555555555555555ull);
     c[0] = low == 0 ? 1u : 0u;
     c[1] = crit_e;
-    c[2] = (uint32_t)__popcll(lower_tris(low)) - tails_t - heads_t;
-    c[3] = (uint32_t)__popc(lower_tets(low)) - tails_t;
+    const uint32_t cells = g_cell_counts.n[low];
+    c[2] = (cells & 0xffu) - tails_t - heads_t;
+    c[3] = (cells >> 8) - tails_t;
 }
 
 __device__ __forceinline__ int64_t box_vertex(int64_t r, int64_t w0, int64_t w1, int64_t lo0,
