@@ -71,20 +71,20 @@ __device__ __forceinline__ int tile_count(int64_t n, int64_t tile)
     return left <= 0 ? 0 : (left < kTile ? (int)left : kTile);
 }
 
-// Histogram update for one item per lane (counts only, no ranks): an LDS
-// atomic per lane, or a single add when the whole wave holds one digit, as
-// it does for the high key bytes of smooth fields.
+// Histogram update for one item per lane (counts only, no ranks), one LDS
+// atomic instruction: the lanes holding the first active lane's digit are
+// counted by a ballot and added once, by that lane; the others add 1 each.
+// Skewed digits (the high bytes of a smooth field) thus cost few same-address
+// atomics.
 __device__ __forceinline__ void hist_add(uint32_t *h, uint32_t d, bool valid)
 {
     const uint64_t act = __ballot(valid);
     if (act == 0) return;
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(valid ? d : 0xffffffffu);
+    const int leader = (int)__builtin_ctzll(act);
+    const uint32_t d0 = __builtin_amdgcn_readlane(d, leader);
     const uint64_t same = __ballot(valid && d == d0);
-    if (same == act) {
-        if (lane_id() == (int)__builtin_ctzll(act)) atomicAdd(&h[d0], (uint32_t)__popcll(act));
-    } else if (valid) {
-        atomicAdd(&h[d], 1u);
-    }
+    const bool lead = lane_id() == leader;
+    if (valid && (d != d0 || lead)) atomicAdd(&h[d], lead ? (uint32_t)__popcll(same) : 1u);
 }
 
 template <typename V, typename K, bool kFirst>
