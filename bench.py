@@ -44,6 +44,24 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic_gb():
+    """HBM bytes per gradient call (GB) from the committed counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2505_21266_amd", "csrc", "dms_gradient.hip")
+    prof = os.path.join(ROOT, "profiles", "traffic_k_gradient_gauss1026.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        m = re.search(r"traffic: kernel=dms_discrete_gradient source_sha256=([0-9a-f]+) "
+                      r"bytes_per_call=(\d+)", open(prof).read())
+    except OSError:
+        return None
+    if not m or m.group(1) != sha:
+        return None
+    return round(int(m.group(2)) / 1e9, 2)
+
+
 def cpu_baseline(field, lo, hi, planes):
     """Times the CPU oracle (order, ProcessLowerStars, extraction) on a slab of
     the same field: `planes` owned z-planes plus their ghost planes."""
@@ -225,12 +243,15 @@ def main():
     ms_step = wall / args.steps * 1e3
     value = owned / (ms_step / 1e3) / 1e9
 
-    # dominant kernel: the single k_gradient launch of dms_discrete_gradient
+    # dominant call: dms_discrete_gradient (k_queue_reset + k_gradient + k_gradient_queue on the
+    # same stream; the events bracket exactly these launches)
     dom = "gradient"
     achieved = ALG_BYTES[dom] * owned / (ms[dom] / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_gradient", "kernel_ms": round(ms[dom], 3)}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic_gb(),
+                "kernel": "dms_discrete_gradient: k_queue_reset + k_gradient<64,16> + k_gradient_queue",
+                "kernel_ms": round(ms[dom], 3)}
     out = {
         "metric": "discrete-gradient Gvertices/s (order + gradient + critical) at 1024^3 owned f32",
         "value": round(value, 3),
