@@ -43,14 +43,18 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *total)
     return before + inc - v;
 }
 
+// Sum of each chunk (order-free, so the loads are striped across the block
+// and coalesced).
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64_t len, T *partials)
 {
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
     T s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < len) s += in[base + k];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k * kScanThreads + threadIdx.x;
+        if (i < len) s += in[i];
+    }
     T total;
     block_exclusive_scan(s, &total);
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
@@ -81,23 +85,39 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(T *partials, int
     }
 }
 
+// Downsweep: the chunk is loaded and stored striped (coalesced) through LDS;
+// each thread scans its kScanItems consecutive elements there.
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(T *data, int64_t len, const T *partials)
 {
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    __shared__ T buf[kScanChunk];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int j = k * kScanThreads + tid;
+        buf[j] = base + j < len ? data[base + j] : T(0);
+    }
+    __syncthreads();
     T v[kScanItems];
     T s = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < len ? data[base + k] : T(0);
+        v[k] = buf[tid * kScanItems + k];
         s += v[k];
     }
     T total;
     T run = partials[blockIdx.x] + block_exclusive_scan(s, &total);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < len) data[base + k] = run;
+        buf[tid * kScanItems + k] = run;
         run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int j = k * kScanThreads + tid;
+        if (base + j < len) data[base + j] = buf[j];
     }
 }
 
