@@ -225,43 +225,58 @@ __device__ __forceinline__ void load_recs(const uint4 *__restrict__ rec, int64_t
 }
 
 // cand (may be null): kCand uint16 tile positions per tile, ncand: their
-// number per tile (the true number, also beyond kCand).
+// number per tile (the true number, also beyond kCand).  Records are read
+// striped (record k * kThreads + tid of the tile), so the loads coalesce;
+// the candidates are listed in record order (row k before row k + 1).
 __global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec, int64_t nbox,
                                                          uint64_t *__restrict__ tile_counts,
                                                          int64_t ntiles, uint16_t *__restrict__ cand,
                                                          uint32_t *__restrict__ ncand)
 {
     __shared__ uint64_t wsum[kThreads / kWave];
-    const int64_t r0 = (int64_t)blockIdx.x * kTileRecs + (int64_t)threadIdx.x * kPerThread;
-    uint64_t lo[kPerThread], hi[kPerThread], pk[kPerThread];
-    load_recs(rec, nbox, r0, lo, hi, pk);
+    const int tid = threadIdx.x;
+    const int64_t t0 = (int64_t)blockIdx.x * kTileRecs;
+    uint64_t pk[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const int64_t r = t0 + k * kThreads + tid;
+        uint32_t c[4] = {0, 0, 0, 0};
+        if (r < nbox) {
+            const uint4 w = rec[r];
+            count_critical((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), c);
+        }
+        pk[k] = pack4(c);
+    }
     uint64_t sum = pk[0] + pk[1] + pk[2] + pk[3];
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-    if (lane_id() == 0) wsum[threadIdx.x / kWave] = sum;
+    if (lane_id() == 0) wsum[tid / kWave] = sum;
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (tid < 4) {
         uint64_t t = 0;
 #pragma unroll
         for (int w = 0; w < kThreads / kWave; ++w) t += wsum[w];
-        tile_counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = lane16(t, threadIdx.x);
+        tile_counts[(int64_t)tid * ntiles + blockIdx.x] = lane16(t, tid);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) tile_counts[4 * ntiles] = 0;
+    if (blockIdx.x == 0 && tid == 0) tile_counts[4 * ntiles] = 0;
     if (cand) {
-        uint32_t mine = 0;
+        // one 16-bit field per row: the row's candidates, scanned over the block
+        uint64_t mine = 0;
 #pragma unroll
-        for (int k = 0; k < kPerThread; ++k) mine += pk[k] != 0 ? 1u : 0u;
-        uint32_t tot;
-        uint32_t a = block_exclusive_scan<uint32_t>(mine, &tot);
+        for (int k = 0; k < kPerThread; ++k) mine |= (uint64_t)(pk[k] != 0 ? 1u : 0u) << (16 * k);
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_scan<uint64_t>(mine, &tot);
+        uint32_t row_base = 0;
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k) {
             if (pk[k] != 0) {
+                const uint32_t a = row_base + lane16(ex, k);
                 if (a < (uint32_t)kCand)
-                    cand[(int64_t)blockIdx.x * kCand + a] = (uint16_t)(threadIdx.x * kPerThread + k);
-                ++a;
+                    cand[(int64_t)blockIdx.x * kCand + a] = (uint16_t)(k * kThreads + tid);
             }
+            row_base += lane16(tot, k);
         }
-        if (threadIdx.x == 0) ncand[blockIdx.x] = tot;
+        if (tid == 0) ncand[blockIdx.x] = row_base;
     }
 }
 
