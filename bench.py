@@ -44,6 +44,26 @@ def parse():
     return ap.parse_args()
 
 
+def copy_bandwidth(dev, mib=4096, reps=5):
+    """Measured streaming bandwidth of a plain device-to-device copy (read +
+    write bytes / time, GB/s), reported next to the 8 TB/s spec peak."""
+    import torch
+    src = torch.empty(mib << 18, dtype=torch.int32, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * mib * (1 << 20) / (ms / 1e3) / 1e9, 1)
+
+
 def measured_traffic_gb():
     """HBM bytes per gradient call (GB) from the committed counter summary,
     or None when the kernel source has changed since the counters were taken."""
@@ -240,6 +260,15 @@ def main():
         stage["gradient"].append(e[1].elapsed_time(e[2]))
         stage["critical"].append(e[2].elapsed_time(e[3]))
     ms = {k: float(np.mean(v)) for k, v in stage.items()}
+    # the equivalent gradient straight from the values (no order needed), same records
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dms.discrete_gradient_values(values, lo, hi, out=rec, workspace=gws, flags=flags, check=False)
+    ev0.record(stream)
+    for _ in range(3):
+        dms.discrete_gradient_values(values, lo, hi, out=rec, workspace=gws, flags=flags, check=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_values_gradient = ev0.elapsed_time(ev1) / 3
     ms_step = wall / args.steps * 1e3
     value = owned / (ms_step / 1e3) / 1e9
 
@@ -270,6 +299,7 @@ def main():
                                % (nx, ny, nz, args.owned, args.bumps),
                    "owned_vertices": owned, "critical_counts": [int(c) for c in cap]},
         "stage_ms": {k: round(v, 3) for k, v in ms.items()},
+        "gradient_from_values_ms": round(ms_values_gradient, 3),
         "stage_frac_hbm": {k: round(ALG_BYTES[k] * owned / (ms[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
                            for k in ms},
         "roofline": roofline,
@@ -277,6 +307,7 @@ def main():
     }
     del values, order_t, rec, lists
     torch.cuda.empty_cache()
+    out["copy_gbs"] = copy_bandwidth(dev)
     if not args.no_extra:
         out["batched"] = bench_batched(dev, max(args.steps, 3))
         out["differentiable"] = bench_differentiable(dev, max(args.steps, 3))

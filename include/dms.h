@@ -124,6 +124,25 @@ int dms_discrete_gradient(const int32_t *order, const int64_t dims[3], const int
                           size_t workspace_bytes, void *stream);
 
 /* ----------------------------------------------------------------------------
+ * Discrete gradient from the values -- the same lower stars, with x and its
+ * neighbours compared by (value, vertex id) directly, as Section 2.1 defines
+ * the order (-0.0 equal to +0.0), instead of through the ranks of the global
+ * order.  Needs no sort (a step the paper's Array Preconditioning performs
+ * once, Section 3), so a block of a larger field can be processed from its
+ * values and ghost layer alone.  The records equal those of
+ * dms_discrete_gradient on the order of the same values, bit for bit.
+ * values: DMS_F32 or DMS_F64 array of the whole grid (dims), device.
+ * dev_flags: DMS_FLAG_NAN is OR-ed in when a value read is NaN (the records
+ * are then undefined).  Other arguments as for dms_discrete_gradient.
+ * Errors: DMS_E_ARG (bad dtype, null values/rec/dev_flags, dims < 1, box
+ * outside the grid), DMS_E_SIZE, DMS_E_WORKSPACE, DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+int dms_discrete_gradient_values(const void *values, int dtype, const int64_t dims[3],
+                                 const int64_t lo[3], const int64_t hi[3], uint32_t *rec,
+                                 void *workspace, size_t workspace_bytes, uint32_t *dev_flags,
+                                 void *stream);
+
+/* ----------------------------------------------------------------------------
  * Critical simplices -- Section 2.6 (zero-persistence skip: every
  * non-critical simplex forms a zero-persistence pair with its vector
  * partner, so only critical simplices go on) and Section 3 (Extract).

@@ -24,6 +24,7 @@ STATUS = {0: "DMS_OK", 1: "DMS_E_ARG", 2: "DMS_E_SIZE", 3: "DMS_E_WORKSPACE",
 # every symbol include/dms.h declares
 SYMBOLS = ("dms_status_str", "dms_version", "dms_star_tables", "dms_order_workspace_size",
            "dms_order", "dms_gradient_workspace_size", "dms_discrete_gradient",
+           "dms_discrete_gradient_values",
            "dms_critical_workspace_size",
            "dms_critical_simplices", "dms_gradient_backward", "dms_d0_pairs_host",
            "dms_batch_create", "dms_batch_workspace_size", "dms_batch_total", "dms_batch_variant",
@@ -59,6 +60,7 @@ def lib():
     L.dms_gradient_workspace_size.argtypes = [P, P, P]
     L.dms_gradient_workspace_size.restype = SZ
     L.dms_discrete_gradient.argtypes = [P, P, P, P, P, P, SZ, P]
+    L.dms_discrete_gradient_values.argtypes = [P, I, P, P, P, P, P, SZ, P, P]
     L.dms_critical_workspace_size.argtypes = [P, P, P]
     L.dms_critical_workspace_size.restype = SZ
     L.dms_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
@@ -73,7 +75,8 @@ def lib():
     L.dms_batch_run.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
     L.dms_batch_destroy.argtypes = [P]
     L.dms_batch_destroy.restype = None
-    for f in ("dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_critical_simplices",
+    for f in ("dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_discrete_gradient_values",
+              "dms_critical_simplices",
               "dms_gradient_backward", "dms_d0_pairs_host", "dms_batch_create", "dms_batch_variant",
               "dms_batch_run"):
         getattr(L, f).restype = I
@@ -164,16 +167,20 @@ def check_flags(flags, allow=0):
     return f
 
 
+def _dtype_code(values):
+    import torch
+    if values.dtype == torch.float32:
+        return DMS_F32
+    if values.dtype == torch.float64:
+        return DMS_F64
+    raise TypeError("values must be float32 or float64")
+
+
 def order(values, out=None, flags=None, check=True):
     """Global vertex order (dms_order): int32 tensor of the values' shape."""
     import torch
     _require_gpu(values, "values")
-    if values.dtype == torch.float32:
-        dt = DMS_F32
-    elif values.dtype == torch.float64:
-        dt = DMS_F64
-    else:
-        raise TypeError("values must be float32 or float64")
+    dt = _dtype_code(values)
     L = lib()
     n = values.numel()
     if out is None:
@@ -239,6 +246,44 @@ def discrete_gradient(order_t, lo=None, hi=None, out=None, queue=True, workspace
                                        _ptr(ws) if ws is not None else None, wbytes,
                                        _stream(order_t)),
            "dms_discrete_gradient")
+    return out
+
+
+def discrete_gradient_values(values, lo=None, hi=None, out=None, queue=True, workspace=None,
+                             flags=None, check=True):
+    """Lower-star records straight from the values (dms_discrete_gradient_values):
+    the same records as discrete_gradient(order(values)), without the sort.
+    Raises on NaN when check (else the caller reads flags)."""
+    import torch
+    _require_gpu(values, "values")
+    dt = _dtype_code(values)
+    dims = dims_of(values)
+    lo, hi = _box(dims, lo, hi)
+    nbox = max(0, (hi[0] - lo[0])) * max(0, (hi[1] - lo[1])) * max(0, (hi[2] - lo[2]))
+    if out is None:
+        out = torch.empty((nbox, 4), dtype=torch.int32, device=values.device)
+    d, dp = _arr3(dims)
+    l, lp = _arr3(lo)
+    h, hp = _arr3(hi)
+    own_flags = flags is None
+    if own_flags:
+        flags = new_flags(values.device)
+    ws, wbytes = None, 0
+    if queue and nbox > 0:
+        wbytes = int(lib().dms_gradient_workspace_size(dp, lp, hp))
+        if workspace is not None:
+            if workspace.numel() < wbytes or not workspace.is_cuda:
+                raise ValueError("gradient workspace too small (%d < %d bytes)"
+                                 % (workspace.numel(), wbytes))
+            ws, wbytes = workspace, workspace.numel()
+        else:
+            ws = torch.empty(wbytes, dtype=torch.uint8, device=values.device)
+    _check(lib().dms_discrete_gradient_values(_ptr(values), dt, dp, lp, hp, _ptr(out),
+                                              _ptr(ws) if ws is not None else None, wbytes,
+                                              _ptr(flags), _stream(values)),
+           "dms_discrete_gradient_values")
+    if check and own_flags:
+        check_flags(flags)
     return out
 
 

@@ -81,8 +81,61 @@ struct Counts {
 
 __device__ __forceinline__ uint32_t nib(uint64_t packed, int i) { return (uint32_t)(packed >> (4 * i)) & 15u; }
 
+// Comparison keys.  The gradient only compares x with its neighbours and
+// the neighbours among themselves, in the order of Section 2.1: by value,
+// ties by vertex id.  Ranks (the global order) are one encoding of it; the
+// values themselves are another (the equivalent form that needs no sort).
+//  RankKeys: the LDS halo holds int32 ranks, compared directly.
+//  F32Keys / F64Keys: the halo holds order-preserving unsigned keys of the
+//    values (-0.0 as +0.0); a comparison value is key << 4 | slot, where the
+//    slot orders x and its neighbours by id (neighbours 0..6 precede x, 7..13
+//    follow it), so equal values break ties by id.
+// Id-order slot of neighbour e relative to x (x itself is slot 7).
+__device__ __forceinline__ constexpr int id_slot(int e) { return e < 7 ? e : e + 1; }
+
+template <typename C>
+__device__ __forceinline__ C cmin(C a, C b) { return b < a ? b : a; }
+
+// A comparison value above every real one.
+template <typename C> __device__ __forceinline__ constexpr C c_highest();
+template <> __device__ __forceinline__ constexpr int32_t c_highest<int32_t>() { return 0x7fffffff; }
+template <> __device__ __forceinline__ constexpr uint64_t c_highest<uint64_t>() { return ~0ull; }
+template <> __device__ __forceinline__ constexpr unsigned __int128 c_highest<unsigned __int128>()
+{
+    return ~(unsigned __int128)0;
+}
+
+struct RankKeys {
+    using H = int32_t;
+    using C = int32_t;
+    static constexpr H kAbsentH = kAbsent;
+    __device__ static H load(const void *f, int64_t i, bool &nan)
+    {
+        nan = false;
+        return ((const int32_t *)f)[i];
+    }
+    __device__ static C cmp(H h, int) { return h; }
+};
+
+struct F32Keys {
+    using H = uint32_t;
+    using C = uint64_t;
+    static constexpr H kAbsentH = 0xffffffffu;  // a NaN's key: never a valid input
+    __device__ static H load(const void *f, int64_t i, bool &nan) { return key_of(((const float *)f)[i], nan); }
+    __device__ static C cmp(H h, int slot) { return h == kAbsentH ? c_highest<C>() : ((C)h << 4) | (C)slot; }
+};
+
+struct F64Keys {
+    using H = uint64_t;
+    using C = unsigned __int128;
+    static constexpr H kAbsentH = ~0ull;
+    __device__ static H load(const void *f, int64_t i, bool &nan) { return key_of(((const double *)f)[i], nan); }
+    __device__ static C cmp(H h, int slot) { return h == kAbsentH ? c_highest<C>() : ((C)h << 4) | (C)slot; }
+};
+
 // Lower-neighbour mask of x: bit e set if neighbour e precedes x.
-__device__ __forceinline__ uint32_t lower_mask(const int32_t *o, int32_t ox)
+template <typename C>
+__device__ __forceinline__ uint32_t lower_mask(const C *o, C ox)
 {
     uint32_t low = 0;
 #pragma unroll
@@ -102,12 +155,14 @@ __device__ __forceinline__ uint64_t lower_star_tq(uint32_t low)
 
 // Ranks of the lower neighbours among themselves, 4 bits per neighbour
 // (15 for a neighbour that is not lower).
-__device__ __forceinline__ uint64_t lower_ranks(const int32_t *o, uint32_t low)
+template <typename C>
+__device__ __forceinline__ uint64_t lower_ranks(const C *o, uint32_t low)
 {
-    uint32_t ol[14], r[14];
+    C ol[14];
+    uint32_t r[14];
 #pragma unroll
     for (int e = 0; e < 14; ++e) {
-        ol[e] = (low >> e) & 1u ? (uint32_t)o[e] : 0xffffffffu;
+        ol[e] = (low >> e) & 1u ? o[e] : c_highest<C>();
         r[e] = 0;
     }
 #pragma unroll
@@ -136,7 +191,8 @@ __device__ __forceinline__ void robins(uint64_t rank_of, int mmax, const SharedT
 
 // Robins' ProcessLowerStars for one vertex, from the orders of x and its 14
 // neighbours (kAbsent for neighbours outside the grid); mmax as in robins.
-__device__ __forceinline__ void process_vertex(const int32_t *o, int32_t ox, int mmax, const SharedTables &T,
+template <typename C>
+__device__ __forceinline__ void process_vertex(const C *o, C ox, int mmax, const SharedTables &T,
                                                uint4 &out)
 {
     const uint32_t low = lower_mask(o, ox);
@@ -309,10 +365,11 @@ __device__ uint4 g_defect6[kDefect6];
 
 // Record of x from one of the tables, or null when x is in none of the
 // families (defect8 may be null: that family then takes the general path).
-__device__ __forceinline__ const uint4 *table_entry(uint32_t low, const int32_t *o,
+template <typename C>
+__device__ __forceinline__ const uint4 *table_entry(uint32_t low, const C *o,
                                                     const uint4 *__restrict__ defect8)
 {
-    constexpr int32_t kHigh = 0x7fffffff;
+    const C kHigh = c_highest<C>();
     const uint32_t rev = __brev(low) >> 18;  // bit e -> bit 13 - e
     const uint32_t one = (low ^ rev) & 0x7fu;
     const int npair = __popc(one);
@@ -324,14 +381,14 @@ __device__ __forceinline__ const uint4 *table_entry(uint32_t low, const int32_t 
     // member of a single pair is the smaller order of the two; a wholly lower
     // pair (side bit set) takes neighbour 13 - i, and neighbour i goes to
     // slot 7
-    int32_t v[8];
-    int32_t v7 = kHigh;
+    C v[8];
+    C v7 = kHigh;
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
-        const int32_t a = o[i], b = o[13 - i];
+        const C a = o[i], b = o[13 - i];
         const bool w = (both >> i) & 1u;
-        v[i] = w ? b : min(a, b);
-        v7 = min(v7, w ? a : kHigh);
+        v[i] = w ? b : cmin(a, b);
+        v7 = cmin(v7, w ? a : kHigh);
     }
     const bool eight = both != 0;
     if (eight && !defect8) return nullptr;
@@ -364,13 +421,17 @@ struct Tile {
     static constexpr int kHalo = HX * HY * HZ;
 };
 
-template <int GX, int GY>
-__device__ __forceinline__ void gather_orders(const int32_t *tile, int c, int32_t *o)
+// Comparison values of x's 14 neighbours (in neighbour order) and of x.
+template <typename Keys, int GX, int GY>
+__device__ __forceinline__ void gather_orders(const typename Keys::H *tile, int c, typename Keys::C *o,
+                                              typename Keys::C &ox)
 {
     using S = Tile<GX, GY>;
 #pragma unroll
     for (int e = 0; e < 14; ++e)
-        o[e] = tile[c + kTables.nb[e][0] + S::HX * (kTables.nb[e][1] + S::HY * kTables.nb[e][2])];
+        o[e] = Keys::cmp(tile[c + kTables.nb[e][0] + S::HX * (kTables.nb[e][1] + S::HY * kTables.nb[e][2])],
+                         id_slot(e));
+    ox = Keys::cmp(tile[c], 7);
 }
 
 // Vertices that no table covers ("general" vertices) need Robins' loop,
@@ -434,43 +495,51 @@ __device__ __forceinline__ uint32_t size_key(uint32_t low)
 // listed.  A tile with fewer than kThreads listed vertices ranks them and
 // queues as many as fit (pairing any others itself); a denser tile sorts
 // them by size and pairs them itself.  Must be entered by the whole block.
-template <int GX, int GY>
-__device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order, int64_t nx,
+template <typename Keys, int GX, int GY>
+__device__ __forceinline__ void gradient_tile(const void *__restrict__ field, int64_t nx,
                                               int64_t ny, int64_t nz, int64_t lo0, int64_t lo1,
                                               int64_t lo2, int64_t w0, int64_t w1, int64_t w2,
                                               int64_t bx, int64_t by, int64_t bz, int64_t rec_off,
                                               uint4 *__restrict__ rec, const uint4 *__restrict__ defect8,
                                               uint4 *__restrict__ queue, uint32_t *qcount, uint32_t qcap,
-                                              BlockShared &sh, int32_t *tile)
+                                              uint32_t *flags, BlockShared &sh,
+                                              typename Keys::H *tile)
 {
     using S = Tile<GX, GY>;
+    using C = typename Keys::C;
     const int tid = threadIdx.x;
     if (tid == 0) sh.nlist = 0;
     const int64_t x0 = lo0 + bx * GX - 1, y0 = lo1 + by * GY - 1, z0 = lo2 + bz - 1;
     const bool full = x0 >= 0 && y0 >= 0 && z0 >= 0 && x0 + S::HX <= nx && y0 + S::HY <= ny &&
                       z0 + S::HZ <= nz;
+    bool nan = false, nan_any = false;
     if (full && nx * S::HY < (1ll << 31)) {
-        // inside the grid: a plane pointer per halo plane (uniform) and a
-        // 32-bit offset within the plane
+        // inside the grid: a plane base per halo plane (uniform) and a 32-bit
+        // offset within the plane
         constexpr int kPlane = S::HX * S::HY;
         const int nxi = (int)nx;
 #pragma unroll
         for (int hz = 0; hz < S::HZ; ++hz) {
-            const int32_t *src = order + (x0 + nx * (y0 + ny * (z0 + hz)));
+            const int64_t base = x0 + nx * (y0 + ny * (z0 + hz));
             for (int i = tid; i < kPlane; i += kThreads) {
                 const int hy = i / S::HX, hx = i - hy * S::HX;
-                tile[hz * kPlane + i] = src[hx + hy * nxi];
+                tile[hz * kPlane + i] = Keys::load(field, base + hx + hy * nxi, nan);
+                nan_any |= nan;
             }
         }
     } else {
         for (int i = tid; i < S::kHalo; i += kThreads) {
             const int hx = i % S::HX, hy = (i / S::HX) % S::HY, hz = i / (S::HX * S::HY);
             const int64_t x = x0 + hx, y = y0 + hy, z = z0 + hz;
-            int32_t v = kAbsent;
-            if (x >= 0 && y >= 0 && z >= 0 && x < nx && y < ny && z < nz) v = order[x + nx * (y + ny * z)];
+            typename Keys::H v = Keys::kAbsentH;
+            if (x >= 0 && y >= 0 && z >= 0 && x < nx && y < ny && z < nz) {
+                v = Keys::load(field, x + nx * (y + ny * z), nan);
+                nan_any |= nan;
+            }
             tile[i] = v;
         }
     }
+    if (flags && __ballot(nan_any) && lane_id() == 0) atomicOr(flags, (uint32_t)DMS_FLAG_NAN);
     __syncthreads();
 
     // pass 1: table vertices; the others are listed
@@ -481,9 +550,9 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
         const int tx = v % GX, ty = v / GX;
         if (bx * GX + tx < w0 && by * GY + ty < w1 && bz < w2) {
             const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
-            int32_t o[14];
-            gather_orders<GX, GY>(tile, c, o);
-            const uint32_t low = lower_mask(o, tile[c]);
+            C o[14], ox;
+            gather_orders<Keys, GX, GY>(tile, c, o, ox);
+            const uint32_t low = lower_mask(o, ox);
             const uint4 *hit = table_entry(low, o, defect8);
             if (hit)
                 rec[rbase + tx + w0 * ty] = *hit;
@@ -502,9 +571,9 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
         const int v = mine ? sh.list[tid] : 0;
         const int tx = v % GX, ty = v / GX;
         const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
-        int32_t o[14];
-        gather_orders<GX, GY>(tile, c, o);
-        const uint32_t low = mine ? lower_mask(o, tile[c]) : 0u;
+        C o[14], ox;
+        gather_orders<Keys, GX, GY>(tile, c, o, ox);
+        const uint32_t low = mine ? lower_mask(o, ox) : 0u;
         const uint64_t rk = mine ? lower_ranks(o, low) : 0xffffffffffffffull;
         __syncthreads();
         // queue as many as fit below qcap, so that every slot the queue
@@ -536,9 +605,9 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
     for (uint32_t i = tid; i < total; i += kThreads) {
         const int v = sh.list[i];
         const int c = (v % GX + 1) + S::HX * ((v / GX + 1) + S::HY);
-        int32_t o[14];
-        gather_orders<GX, GY>(tile, c, o);
-        atomicAdd(&sh.bins[size_key(lower_mask(o, tile[c]))], 1u);
+        C o[14], ox;
+        gather_orders<Keys, GX, GY>(tile, c, o, ox);
+        atomicAdd(&sh.bins[size_key(lower_mask(o, ox))], 1u);
     }
     __syncthreads();
     scan_bins(sh.bins);
@@ -546,9 +615,9 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
     for (uint32_t i = tid; i < total; i += kThreads) {
         const int v = sh.list[i];
         const int c = (v % GX + 1) + S::HX * ((v / GX + 1) + S::HY);
-        int32_t o[14];
-        gather_orders<GX, GY>(tile, c, o);
-        sh.perm[atomicAdd(&sh.bins[size_key(lower_mask(o, tile[c]))], 1u)] = (uint16_t)v;
+        C o[14], ox;
+        gather_orders<Keys, GX, GY>(tile, c, o, ox);
+        sh.perm[atomicAdd(&sh.bins[size_key(lower_mask(o, ox))], 1u)] = (uint16_t)v;
     }
     __syncthreads();
 
@@ -559,23 +628,25 @@ __device__ __forceinline__ void gradient_tile(const int32_t *__restrict__ order,
         const int v = active ? sh.perm[i] : 0;
         const int tx = v % GX, ty = v / GX;
         const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
-        int32_t o[14];
-        gather_orders<GX, GY>(tile, c, o);
-        const int m = active ? __popc(lower_mask(o, tile[c])) : 0;
+        C o[14], ox;
+        gather_orders<Keys, GX, GY>(tile, c, o, ox);
+        const int m = active ? __popc(lower_mask(o, ox)) : 0;
         int mmax = m;
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
         mmax = __builtin_amdgcn_readfirstlane(mmax);
         if (active) {
             uint4 r;
-            process_vertex(o, tile[c], mmax, sh.T, r);
+            process_vertex(o, ox, mmax, sh.T, r);
             rec[rbase + tx + w0 * ty] = r;
         }
     }
 }
 
-template <int GX, int GY>
-__global__ __launch_bounds__(kThreads, 8) void k_gradient(const int32_t *__restrict__ order,
+// Keys: RankKeys reads the int32 order; F32Keys / F64Keys read the values
+// (flags receives DMS_FLAG_NAN for a NaN among them).
+template <typename Keys, int GX, int GY>
+__global__ __launch_bounds__(kThreads, 8) void k_gradient(const void *__restrict__ field,
                                                        int64_t nx, int64_t ny, int64_t nz,
                                                        int64_t lo0, int64_t lo1, int64_t lo2,
                                                        int64_t w0, int64_t w1, int64_t w2,
@@ -583,15 +654,15 @@ __global__ __launch_bounds__(kThreads, 8) void k_gradient(const int32_t *__restr
                                                        uint4 *__restrict__ rec,
                                                        const uint4 *__restrict__ defect8,
                                                        uint4 *__restrict__ queue, uint32_t *qcount,
-                                                       uint32_t qcap)
+                                                       uint32_t qcap, uint32_t *flags)
 {
     __shared__ BlockShared sh;
-    __shared__ int32_t tile[Tile<GX, GY>::kHalo];
+    __shared__ typename Keys::H tile[Tile<GX, GY>::kHalo];
     load_tables(sh.T);
     const int64_t b = blockIdx.x;
     const int64_t bx = b % bx_count, by = (b / bx_count) % by_count, bz = b / (bx_count * by_count);
-    gradient_tile<GX, GY>(order, nx, ny, nz, lo0, lo1, lo2, w0, w1, w2, bx, by, bz, 0, rec, defect8,
-                          queue, qcount, qcap, sh, tile);
+    gradient_tile<Keys, GX, GY>(field, nx, ny, nz, lo0, lo1, lo2, w0, w1, w2, bx, by, bz, 0, rec, defect8,
+                                queue, qcount, qcap, flags, sh, tile);
 }
 
 // Batched form: many whole fields, concatenated; a persistent grid walks the
@@ -623,8 +694,9 @@ __global__ __launch_bounds__(kThreads, 5) void k_gradient_batch(const int32_t *_
         const int64_t bxc = (F.n[0] + GX - 1) / GX, byc = (F.n[1] + GY - 1) / GY;
         const int64_t k = t - tstart[lo];
         const int64_t bx = k % bxc, by = (k / bxc) % byc, bz = k / (bxc * byc);
-        gradient_tile<GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1], F.n[2],
-                              bx, by, bz, F.off, rec, defect8, queue, qcount, qcap, sh, tile);
+        gradient_tile<RankKeys, GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1],
+                                        F.n[2], bx, by, bz, F.off, rec, defect8, queue, qcount, qcap,
+                                        nullptr, sh, tile);
         __syncthreads();  // the next tile reuses the shared buffers
     }
 }
@@ -853,8 +925,10 @@ static void queue_finish(const uint4 *queue, const uint32_t *qcount, uint32_t qc
                        (uint4 *)rec);
 }
 
-int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
-                    const int64_t *hi, uint32_t *rec, char *ws, hipStream_t s)
+template <typename Keys>
+static int launch_gradient_keys(int variant, const void *field, const int64_t *dims, const int64_t *lo,
+                                const int64_t *hi, uint32_t *rec, char *ws, uint32_t *flags,
+                                hipStream_t s)
 {
     const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
     if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
@@ -867,9 +941,9 @@ int launch_gradient(int variant, const int32_t *order, const int64_t *dims, cons
     uint32_t *qcount, qcap;
     queue_begin(ws, w0 * w1 * w2, s, &queue, &qcount, &qcap);
 #define DMS_LAUNCH(GXV)                                                                              \
-    hipLaunchKernelGGL((k_gradient<GXV, kTileVerts / GXV>), dim3((unsigned)blocks), dim3(kThreads), 0, s, \
-                       order, dims[0], dims[1], dims[2], lo[0], lo[1], lo[2], w0, w1, w2, bxc, byc,  \
-                       (uint4 *)rec, d8, queue, qcount, qcap)
+    hipLaunchKernelGGL((k_gradient<Keys, GXV, kTileVerts / GXV>), dim3((unsigned)blocks), dim3(kThreads), \
+                       0, s, field, dims[0], dims[1], dims[2], lo[0], lo[1], lo[2], w0, w1, w2, bxc, byc, \
+                       (uint4 *)rec, d8, queue, qcount, qcap, flags)
     switch (variant) {
     case 0: DMS_LAUNCH(64); break;
     case 1: DMS_LAUNCH(32); break;
@@ -878,6 +952,12 @@ int launch_gradient(int variant, const int32_t *order, const int64_t *dims, cons
 #undef DMS_LAUNCH
     queue_finish(queue, qcount, qcap, rec, s);
     return launch_status();
+}
+
+int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
+                    const int64_t *hi, uint32_t *rec, char *ws, hipStream_t s)
+{
+    return launch_gradient_keys<RankKeys>(variant, order, dims, lo, hi, rec, ws, nullptr, s);
 }
 
 int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
@@ -927,4 +1007,26 @@ extern "C" int dms_discrete_gradient(const int32_t *order, const int64_t dims[3]
     const int st = ensure_regular_table((hipStream_t)stream);
     if (st) return st;
     return launch_gradient(0, order, dims, lo, hi, rec, (char *)workspace, (hipStream_t)stream);
+}
+
+extern "C" int dms_discrete_gradient_values(const void *values, int dtype, const int64_t dims[3],
+                                            const int64_t lo[3], const int64_t hi[3], uint32_t *rec,
+                                            void *workspace, size_t workspace_bytes,
+                                            uint32_t *dev_flags, void *stream)
+{
+    using namespace dms;
+    if (dtype != DMS_F32 && dtype != DMS_F64) return DMS_E_ARG;
+    if (!box_valid(dims, lo, hi)) return DMS_E_ARG;
+    if (!grid_size_ok(dims)) return DMS_E_SIZE;
+    const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
+    if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
+    if (!values || !rec || !dev_flags) return DMS_E_ARG;
+    if (workspace && workspace_bytes < gradient_workspace_size(w0 * w1 * w2)) return DMS_E_WORKSPACE;
+    const int st = ensure_regular_table((hipStream_t)stream);
+    if (st) return st;
+    if (dtype == DMS_F32)
+        return launch_gradient_keys<F32Keys>(0, values, dims, lo, hi, rec, (char *)workspace, dev_flags,
+                                             (hipStream_t)stream);
+    return launch_gradient_keys<F64Keys>(0, values, dims, lo, hi, rec, (char *)workspace, dev_flags,
+                                         (hipStream_t)stream);
 }

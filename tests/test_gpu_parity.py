@@ -191,6 +191,52 @@ def test_gradient_queue_paths():
         assert (got == want).all(), queue
 
 
+# the gradient straight from the values: (value, id) comparisons instead of
+# ranks must give the same records -- ties (integer fields, +-0.0) exercise
+# the id tie-break
+VALUE_CASES = [
+    ((64, 64, 64), "noise", 41),
+    ((70, 9, 6), "ties", 42),
+    ((33, 17, 12), "mixture", 43),
+    ((45, 37, 29), "f64", 44),
+    ((160, 96, 12), "ramp2.5", 45),
+    ((9, 1, 1), "ties", 46),
+]
+
+
+@pytest.mark.parametrize("dims,kind,seed", VALUE_CASES)
+def test_gradient_from_values(dims, kind, seed):
+    v = _field(dims, kind, seed)
+    o = oracle.order(v)
+    want, _, _ = oracle.lower_stars(o, dims)
+    _say("gradient from values", dims, kind)
+    got = dms.discrete_gradient_values(_dev(v)).cpu().numpy().view(np.uint32)
+    assert (got == want).all()
+    got2 = dms.discrete_gradient_values(_dev(v), queue=False).cpu().numpy().view(np.uint32)
+    assert (got2 == want).all()
+
+
+def test_gradient_from_values_signed_zero_box():
+    """-0.0 and +0.0 are one value (ties by id); an owned box of a ghosted
+    block reads its ghosts."""
+    dims = (30, 20, 10)
+    rng = np.random.default_rng(47)
+    v = rng.integers(-2, 3, (10, 20, 30)).astype(np.float32)
+    v[v == 0] = np.where(rng.random(int((v == 0).sum())) < 0.5, -0.0, 0.0).astype(np.float32)
+    lo, hi = (1, 1, 1), (29, 19, 9)
+    o = oracle.order(v)
+    want, _, _ = oracle.lower_stars(o, dims, lo, hi)
+    got = dms.discrete_gradient_values(_dev(v), lo, hi).cpu().numpy().view(np.uint32)
+    assert (got == want).all()
+
+
+def test_gradient_from_values_nan_flag():
+    v = np.random.default_rng(48).random((12, 12, 12)).astype(np.float32)
+    v[5, 6, 7] = np.nan
+    with pytest.raises(ValueError):
+        dms.discrete_gradient_values(_dev(v))
+
+
 @pytest.mark.parametrize("dims,lo,hi", [((20, 18, 16), (1, 2, 1), (19, 17, 15)),
                                         ((66, 10, 7), (1, 1, 1), (65, 9, 6)),
                                         ((30, 30, 30), (0, 0, 0), (30, 1, 30)),

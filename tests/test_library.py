@@ -84,6 +84,14 @@ def test_argument_errors(L):
     assert need >= 256 + 16 * 1024
     assert L.dms_discrete_gradient(fake, dp, lp, hp, fake, fake, need - 1, None) == 3
     assert L.dms_gradient_workspace_size(dp, lp, badp) == 0
+    # gradient from the values
+    assert L.dms_discrete_gradient_values(fake, 7, dp, lp, hp, fake, None, 0, fake, None) == 1
+    assert L.dms_discrete_gradient_values(None, 0, dp, lp, hp, fake, None, 0, fake, None) == 1
+    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, None, 0, None, None) == 1
+    assert L.dms_discrete_gradient_values(fake, 1, dp, lp, badp, fake, None, 0, fake, None) == 1
+    assert L.dms_discrete_gradient_values(fake, 0, bigp, lp, hp, fake, None, 0, fake, None) == 2
+    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, fake, need - 1, fake, None) == 3
+    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, lp, fake, None, 0, fake, None) == 0
     # critical
     cap, capp = _a3([0, 0, 0, 0])
     assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, capp, fake, fake, 0,
