@@ -145,7 +145,9 @@ def bench_batched(dev, reps):
 
 def bench_differentiable(dev, reps):
     """128^3 float64 field (16 Gaussians + 1e-4 noise, min gap 1e-9): GPU
-    forward (order, gradient, extraction), host D0 pairing, GPU backward."""
+    forward (order, gradient, extraction), D0 pairing (extremum graph on the
+    GPU, union-find on the host), GPU backward.  The all-host pairing is
+    timed beside it for comparison."""
     import torch
 
     import paper_2505_21266_amd as dms
@@ -159,7 +161,7 @@ def bench_differentiable(dev, reps):
     lists, counts = dms.critical_simplices(rec, dims)
     cap = counts.cpu().numpy()
     torch.cuda.synchronize()
-    fwd, host, bwd = [], [], []
+    fwd, host, bwd, allhost = [], [], [], []
     for _ in range(reps):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         e[0].record()
@@ -169,9 +171,14 @@ def bench_differentiable(dev, reps):
         e[1].record()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pe, pm = dms.d0_pairs_host(rec.cpu().numpy(), o.cpu().numpy().reshape(-1), dims,
-                                   lists[1].cpu().numpy())
+        pe, pm = dms.d0_pairs(rec, o, dims, lists[0], lists[1])
         t1 = time.perf_counter()
+        t2 = time.perf_counter()
+        pe2, pm2 = dms.d0_pairs_host(rec.cpu().numpy(), o.cpu().numpy().reshape(-1), dims,
+                                     lists[1].cpu().numpy())
+        allhost.append((time.perf_counter() - t2) * 1e3)
+        if not ((pe2 == pe).all() and (pm2 == pm).all()):
+            raise RuntimeError("D0 pairings disagree")
         dc = torch.from_numpy(pe).to(dev)
         bc = torch.from_numpy(pm).to(dev) << 8
         flat = x.reshape(-1)
@@ -187,7 +194,8 @@ def bench_differentiable(dev, reps):
         host.append((t1 - t0) * 1e3)
         bwd.append(e[2].elapsed_time(e[3]))
     return {"vertices": n, "pairs": int(pe.size), "forward_gpu_ms": round(float(np.median(fwd)), 3),
-            "host_d0_ms": round(float(np.median(host)), 3),
+            "d0_ms": round(float(np.median(host)), 3),
+            "d0_all_host_ms": round(float(np.median(allhost)), 3),
             "backward_gpu_ms": round(float(np.median(bwd)), 4), "reps": reps}
 
 

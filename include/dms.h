@@ -241,6 +241,43 @@ int dms_batch_run(dms_batch *batch, const void *values, int32_t *order, uint32_t
                   uint32_t *dev_flags, void *stream);
 void dms_batch_destroy(dms_batch *batch);
 
+/* ----------------------------------------------------------------------------
+ * D0 pairing on the GPU, extremum-graph half -- Section 2.6 (for each
+ * critical edge, the minima reached by descending from its two vertices along
+ * the vertex-edge vectors) and the visiting order of Algorithm 1 (increasing
+ * edge, Section 2.1 comparison).
+ *
+ * rec: the records of the WHOLE grid (dms_discrete_gradient with the box equal
+ * to the grid); order: the grid's order; crit0 / crit1: its critical vertex
+ * and edge codes (dms_critical_simplices).  All device arrays.
+ * Outputs (device): tri_edge, tri_min0, tri_min1 [capacity n1]: the triplets
+ * whose two minima differ, sorted by edge; tri_min* are indices into crit0
+ * (the minimum reached from the edge's higher vertex first); min_order[n0]:
+ * the order of each minimum; *ntri: the number of triplets (int64).
+ * workspace: dms_d0_workspace_size(dims, n1) bytes.  A minimum missing from
+ * crit0 (a truncated list) sets DMS_FLAG_CAPACITY in *dev_flags.
+ * Errors: DMS_E_ARG, DMS_E_SIZE, DMS_E_WORKSPACE, DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+size_t dms_d0_workspace_size(const int64_t dims[3], int64_t n1);
+int dms_d0_triplets(const uint32_t *rec, const int32_t *order, const int64_t dims[3],
+                    const int64_t *crit0, int64_t n0, const int64_t *crit1, int64_t n1,
+                    int64_t *tri_edge, int32_t *tri_min0, int32_t *tri_min1, int32_t *min_order,
+                    int64_t *ntri, void *workspace, size_t workspace_bytes, uint32_t *dev_flags,
+                    void *stream);
+
+/* ----------------------------------------------------------------------------
+ * D0 pairing, union-find half -- Algorithm 1 (PairExtremaSaddles) over the
+ * sorted triplets of dms_d0_triplets, on [host] arrays: each triplet joins
+ * the classes of its minima; the younger representative (higher order) dies
+ * at the edge.  Outputs pair_edge (edge codes) and pair_min (indices into
+ * crit0) in visiting order, up to capacity; *npairs is the exact count.
+ * Errors: DMS_E_ARG (bad arguments or a minimum index outside [0, n0)),
+ * DMS_E_WORKSPACE (more pairs than capacity; npairs is still exact).
+ * -------------------------------------------------------------------------- */
+int dms_d0_pairs_sorted_host(const int64_t *tri_edge, const int32_t *tri_min0, const int32_t *tri_min1,
+                             int64_t ntri, const int32_t *min_order, int64_t n0, int64_t *pair_edge,
+                             int32_t *pair_min, int64_t capacity, int64_t *npairs);
+
 #ifdef __cplusplus
 }
 #endif

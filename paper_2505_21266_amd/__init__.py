@@ -28,7 +28,8 @@ SYMBOLS = ("dms_status_str", "dms_version", "dms_star_tables", "dms_order_worksp
            "dms_critical_workspace_size",
            "dms_critical_simplices", "dms_gradient_backward", "dms_d0_pairs_host",
            "dms_batch_create", "dms_batch_workspace_size", "dms_batch_total", "dms_batch_variant",
-           "dms_batch_run", "dms_batch_destroy")
+           "dms_batch_run", "dms_batch_destroy", "dms_d0_workspace_size", "dms_d0_triplets",
+           "dms_d0_pairs_sorted_host")
 
 _lib = None
 
@@ -75,8 +76,12 @@ def lib():
     L.dms_batch_run.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
     L.dms_batch_destroy.argtypes = [P]
     L.dms_batch_destroy.restype = None
+    L.dms_d0_workspace_size.argtypes = [P, I64]
+    L.dms_d0_workspace_size.restype = SZ
+    L.dms_d0_triplets.argtypes = [P, P, P, P, I64, P, I64, P, P, P, P, P, P, SZ, P, P]
+    L.dms_d0_pairs_sorted_host.argtypes = [P, P, P, I64, P, I64, P, P, I64, P]
     for f in ("dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_discrete_gradient_values",
-              "dms_critical_simplices",
+              "dms_critical_simplices", "dms_d0_triplets", "dms_d0_pairs_sorted_host",
               "dms_gradient_backward", "dms_d0_pairs_host", "dms_batch_create", "dms_batch_variant",
               "dms_batch_run"):
         getattr(L, f).restype = I
@@ -361,6 +366,47 @@ def d0_pairs_host(rec_np, order_np, dims, crit1_np):
            "dms_d0_pairs_host")
     k = int(npairs[0])
     return pe[:k], pm[:k]
+
+
+def d0_pairs(rec, order_t, dims, crit0, crit1):
+    """D0 pairing: the extremum graph on the GPU (dms_d0_triplets: descents by
+    pointer doubling, triplets sorted by edge), Algorithm 1 on the host
+    (dms_d0_pairs_sorted_host).  rec/order_t/crit0/crit1 are device tensors
+    of the whole grid.  Returns numpy (pair_edge codes, pair_min vertices)."""
+    import torch
+    L = lib()
+    P = ctypes.c_void_p
+    dev = rec.device
+    n0, n1 = int(crit0.numel()), int(crit1.numel())
+    d, dp = _arr3(dims)
+    tri_edge = torch.empty(max(n1, 1), dtype=torch.int64, device=dev)
+    tri_min0 = torch.empty(max(n1, 1), dtype=torch.int32, device=dev)
+    tri_min1 = torch.empty(max(n1, 1), dtype=torch.int32, device=dev)
+    min_order = torch.empty(max(n0, 1), dtype=torch.int32, device=dev)
+    ntri = torch.zeros(1, dtype=torch.int64, device=dev)
+    flags = new_flags(dev)
+    ws = torch.empty(max(int(L.dms_d0_workspace_size(dp, n1)), 256), dtype=torch.uint8, device=dev)
+    _check(L.dms_d0_triplets(_ptr(rec), _ptr(order_t), dp, _ptr(crit0), n0, _ptr(crit1), n1,
+                             _ptr(tri_edge), _ptr(tri_min0), _ptr(tri_min1), _ptr(min_order),
+                             _ptr(ntri), _ptr(ws), ws.numel(), _ptr(flags), _stream(rec)),
+           "dms_d0_triplets")
+    check_flags(flags)
+    k = int(ntri.item())
+    te = np.ascontiguousarray(tri_edge[:k].cpu().numpy())
+    t0 = np.ascontiguousarray(tri_min0[:k].cpu().numpy())
+    t1 = np.ascontiguousarray(tri_min1[:k].cpu().numpy())
+    mo = np.ascontiguousarray(min_order[:n0].cpu().numpy())
+    c0 = crit0.cpu().numpy()
+    cap = max(k, 1)
+    pe = np.zeros(cap, np.int64)
+    pm = np.zeros(cap, np.int32)
+    npairs = np.zeros(1, np.int64)
+    _check(L.dms_d0_pairs_sorted_host(te.ctypes.data_as(P), t0.ctypes.data_as(P), t1.ctypes.data_as(P),
+                                      k, mo.ctypes.data_as(P), n0, pe.ctypes.data_as(P),
+                                      pm.ctypes.data_as(P), cap, npairs.ctypes.data_as(P)),
+           "dms_d0_pairs_sorted_host")
+    m = int(npairs[0])
+    return pe[:m], (c0[pm[:m]] >> 8).astype(np.int64)
 
 
 def gradient_pipeline(values, lo=None, hi=None, cap=None):

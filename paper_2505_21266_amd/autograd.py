@@ -1,9 +1,10 @@
 """Differentiable D0 persistence of a scalar field on the GPU path.
 
 Forward (Section 2.5, 2.6): GPU order, discrete gradient and critical
-simplices; the records, order and critical edges go to the host, where the
-library's D0 pairing (Algorithm 1) runs; births and deaths are gathered from
-the field as the highest vertex value of each simplex.  Backward: the
+simplices; the extremum graph (descents from the critical edges, triplets
+sorted by edge) on the GPU, Algorithm 1's union-find on the host over the
+sorted triplets; births and deaths are gathered from the field as the
+highest vertex value of each simplex.  Backward: the
 library's scatter kernel sends dL/d(birth, death) to the max vertices.
 """
 import numpy as np
@@ -16,7 +17,7 @@ def _torch():
 
 def _make():
     torch = _torch()
-    from . import critical_simplices, d0_pairs_host, discrete_gradient, dims_of, gradient_backward, order
+    from . import critical_simplices, d0_pairs, discrete_gradient, dims_of, gradient_backward, order
 
     class PersistenceD0(torch.autograd.Function):
         """apply(field) -> (births, deaths): float tensors of the finite D0
@@ -29,8 +30,7 @@ def _make():
                 o = order(field)
                 rec = discrete_gradient(o)
                 lists, counts = critical_simplices(rec, dims)
-                pe, pm = d0_pairs_host(rec.cpu().numpy(), o.cpu().numpy().reshape(-1), dims,
-                                       lists[1].cpu().numpy())
+                pe, pm = d0_pairs(rec, o, dims, lists[0], lists[1])
             dev = field.device
             death_code = torch.from_numpy(pe).to(dev)
             birth_vertex = torch.from_numpy(pm).to(dev)

@@ -57,6 +57,14 @@ __device__ __forceinline__ uint32_t key_of(float v, bool &nan)
     return b ^ ((b & 0x80000000u) ? 0xffffffffu : 0x80000000u);
 }
 
+// Unsigned 64-bit integers are their own keys (used to sort composite
+// integer keys with the same passes).
+__device__ __forceinline__ uint64_t key_of(uint64_t v, bool &nan)
+{
+    nan = false;
+    return v;
+}
+
 __device__ __forceinline__ uint64_t key_of(double v, bool &nan)
 {
     uint64_t b = (uint64_t)__double_as_longlong(v);

@@ -95,3 +95,41 @@ extern "C" int dms_d0_pairs_host(const uint32_t *rec, const int32_t *order, cons
     *npairs = np;
     return np > capacity ? DMS_E_WORKSPACE : DMS_OK;
 }
+
+// Algorithm 1 on triplets already in increasing edge order (dms_d0_triplets):
+// minima are indices 0..n0-1 of the critical-vertex list, min_order their
+// orders.  pair_min receives minimum indices.
+extern "C" int dms_d0_pairs_sorted_host(const int64_t *tri_edge, const int32_t *tri_min0,
+                                        const int32_t *tri_min1, int64_t ntri, const int32_t *min_order,
+                                        int64_t n0, int64_t *pair_edge, int32_t *pair_min,
+                                        int64_t capacity, int64_t *npairs)
+{
+    if (!npairs || ntri < 0 || n0 < 0 || capacity < 0) return DMS_E_ARG;
+    if (ntri > 0 && (!tri_edge || !tri_min0 || !tri_min1)) return DMS_E_ARG;
+    if (n0 > 0 && !min_order) return DMS_E_ARG;
+    if (capacity > 0 && (!pair_edge || !pair_min)) return DMS_E_ARG;
+    std::vector<int32_t> rep((size_t)n0);
+    for (int64_t i = 0; i < n0; ++i) rep[(size_t)i] = (int32_t)i;
+    auto find = [&](int32_t v) {
+        while (rep[(size_t)v] != v) v = rep[(size_t)v];
+        return v;
+    };
+    int64_t np = 0;
+    for (int64_t j = 0; j < ntri; ++j) {
+        const int32_t t0 = tri_min0[j], t1 = tri_min1[j];
+        if (t0 < 0 || t1 < 0 || t0 >= n0 || t1 >= n0) return DMS_E_ARG;
+        int32_t r0 = find(t0), r1 = find(t1);
+        if (r0 == r1) continue;
+        if (min_order[r0] < min_order[r1]) std::swap(r0, r1);
+        if (np < capacity) {
+            pair_edge[np] = tri_edge[j];
+            pair_min[np] = r0;
+        }
+        ++np;
+        rep[(size_t)r0] = r1;
+        rep[(size_t)t0] = r1;
+    }
+    *npairs = np;
+    return np > capacity ? DMS_E_WORKSPACE : DMS_OK;
+}
+

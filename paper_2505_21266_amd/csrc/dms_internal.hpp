@@ -32,6 +32,12 @@ int launch_gradient_batch(int variant, const int32_t *order, const BatchField *f
                           const int64_t *tile_start, int64_t total_tiles, int64_t total_verts,
                           uint32_t *rec, int grid, char *ws, hipStream_t s);
 
+// Ranks of n 64-bit unsigned keys (rank[i] = position of key i in the
+// ascending stable sort), with the order passes.
+size_t rank_u64_workspace_size(int64_t n);
+int launch_rank_u64(const uint64_t *keys, int64_t n, int32_t *rank, char *ws, uint32_t *flags,
+                    hipStream_t s);
+
 // Batched order: values of all fields concatenated (float32); the field of
 // element i is the f with foff[f] <= i < foff[f + 1] (foff on the device).
 size_t order_batch_workspace_size(int64_t n);

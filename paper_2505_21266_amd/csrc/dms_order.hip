@@ -680,6 +680,15 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
 
 }  // namespace
 
+size_t rank_u64_workspace_size(int64_t n) { return order_layout<uint64_t>(n > 0 ? n : 1).total; }
+
+int launch_rank_u64(const uint64_t *keys, int64_t n, int32_t *rank, char *ws, uint32_t *flags,
+                    hipStream_t s)
+{
+    if (n == 0) return DMS_OK;
+    return run_order<uint64_t, uint64_t>(keys, n, 8, rank, ws, flags, nullptr, 0, s);
+}
+
 size_t order_batch_workspace_size(int64_t n) { return order_layout<uint64_t>(n > 0 ? n : 1).total; }
 
 int launch_order_batch(const float *values, int64_t n, const int64_t *foff, int nfields,

@@ -352,6 +352,29 @@ def test_backward_matches_oracle(shape):
     assert scale > 0
 
 
+@pytest.mark.parametrize("shape,kind,seed", [((24, 20, 16), "noise", 61), ((32, 32, 32), "f64", 62),
+                                             ((18, 30, 9), "ties", 63), ((40, 1, 7), "noise", 64)])
+def test_d0_pairs_gpu_matches_oracle(shape, kind, seed):
+    """GPU extremum graph + host union-find give the oracle's D0 pairs, in
+    the same order (Section 2.6, Algorithm 1)."""
+    nz, ny, nx = shape
+    v = _field((nx, ny, nz), kind, seed)
+    if kind == "f64":
+        v = inputs.min_gap_pass(v)
+    dims = (nx, ny, nz)
+    o = oracle.order(v)
+    rec, _, _ = oracle.lower_stars(o, dims)
+    crit, _ = oracle.critical_simplices(rec, dims)
+    pe_o, pm_o = oracle.d0_pairs(o, rec, dims, crit[1])
+    _say("d0 gpu", shape, kind)
+    og = dms.order(_dev(v))
+    rg = dms.discrete_gradient(og)
+    lists, counts = dms.critical_simplices(rg, dims)
+    pe, pm = dms.d0_pairs(rg, og, dims, lists[0], lists[1])
+    assert (pe == pe_o).all() and (pm == pm_o).all()
+    assert len(pe) == len(crit[0]) - 1  # every minimum but one dies (one component)
+
+
 def test_backward_kernel_runs():
     # several deaths on one vertex, given adjacent: summed in pair order
     bc = _dev(np.array([5 << 8, 9 << 8, 11 << 8], np.int64))

@@ -128,3 +128,30 @@ def test_host_d0_errors(L):
     rec = np.zeros((64, 4), np.uint32)
     with pytest.raises(dms.DmsError):
         dms.d0_pairs_host(rec, o, dims, np.array([(100 << 8) | 3], np.int64))
+
+
+def test_d0_pairs_sorted_host_hand_case():
+    """Algorithm 1 on three minima (orders 5, 1, 9) and three sorted triplets,
+    worked by hand: edge 100 joins minima 0 and 1, the younger (0, order 5)
+    dies; edge 200 joins 2 and the class of 0 (representative 1), 2 dies;
+    edge 300 joins 1 and 2, already one class."""
+    L = dms.lib()
+    P = ctypes.c_void_p
+    te = np.array([100, 200, 300], np.int64)
+    t0 = np.array([0, 2, 1], np.int32)
+    t1 = np.array([1, 0, 2], np.int32)
+    mo = np.array([5, 1, 9], np.int32)
+    pe = np.zeros(3, np.int64)
+    pm = np.zeros(3, np.int32)
+    npairs = np.zeros(1, np.int64)
+    st = L.dms_d0_pairs_sorted_host(te.ctypes.data_as(P), t0.ctypes.data_as(P), t1.ctypes.data_as(P), 3,
+                                    mo.ctypes.data_as(P), 3, pe.ctypes.data_as(P), pm.ctypes.data_as(P), 3,
+                                    npairs.ctypes.data_as(P))
+    assert st == 0 and int(npairs[0]) == 2
+    assert pe[:2].tolist() == [100, 200] and pm[:2].tolist() == [0, 2]
+    # a minimum index outside [0, n0) is an argument error
+    bad = np.array([0, 7, 1], np.int32)
+    assert L.dms_d0_pairs_sorted_host(te.ctypes.data_as(P), bad.ctypes.data_as(P), t1.ctypes.data_as(P), 3,
+                                      mo.ctypes.data_as(P), 3, pe.ctypes.data_as(P), pm.ctypes.data_as(P),
+                                      3, npairs.ctypes.data_as(P)) == 1
+
