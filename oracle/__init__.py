@@ -18,6 +18,7 @@ Functions:
   critical_simplices(...)    zero-persistence skip -> 4 code lists
   d0_pairs(...)              Algorithm 1 on the extremum graph
   d0_loss_grad(...)          loss of the differentiable form and its gradient
+  filtration_sort(...)       critical cells of one dimension in filtration order
 """
 import ctypes
 import os
@@ -66,9 +67,11 @@ def _load():
     lib.oracle_decode_record.argtypes = [P, P]
     lib.oracle_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P]
     lib.oracle_d0_pairs.argtypes = [P, P, P, P, I64, P, P, P]
+    lib.oracle_filtration_sort.argtypes = [P, P, P, I64, I, P]
     for f in (lib.oracle_star_tables, lib.oracle_order_f32, lib.oracle_order_f64,
               lib.oracle_pls_local, lib.oracle_lower_stars, lib.oracle_lower_stars_sampled,
-              lib.oracle_decode_record, lib.oracle_critical_simplices, lib.oracle_d0_pairs):
+              lib.oracle_decode_record, lib.oracle_critical_simplices, lib.oracle_d0_pairs,
+              lib.oracle_filtration_sort):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -242,3 +245,17 @@ def d0_loss_grad(values_f64, pair_edge, pair_min, threshold=0.05):
     np.add.at(grad, dv[keep], 2.0 * pers[keep])
     np.add.at(grad, bv[keep], -2.0 * pers[keep])
     return loss, grad, keep
+
+
+def filtration_sort(order_arr, dims, codes, dim):
+    """Critical cells of dimension dim, as (maxv << 8) | local index codes,
+    sorted in the filtration order of Section 2.1 (decreasing vertex-order
+    lists compared lexicographically)."""
+    lib = _load()
+    o = np.ascontiguousarray(order_arr, dtype=np.int32).reshape(-1)
+    c = _i64(codes).reshape(-1)
+    out = np.zeros(max(c.size, 1), np.int64)
+    rc = lib.oracle_filtration_sort(_p(o), _p(_i64(dims)), _p(c), c.size, int(dim), _p(out))
+    if rc != 0:
+        raise ValueError("oracle filtration sort failed (%d)" % rc)
+    return out[:c.size].copy()

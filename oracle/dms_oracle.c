@@ -789,3 +789,74 @@ int oracle_d0_pairs(const int32_t *order, const uint32_t *rec, const int64_t *di
     free(rep);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* O-7  Critical cells in filtration order (Section 2.1).  Two cells of one */
+/* dimension compare by the lists of their vertex orders, each sorted       */
+/* decreasingly, lexicographically; distinct cells have distinct lists, so  */
+/* the sorted result is unique.  Input codes are (maxv << 8) | local index  */
+/* as O-5 writes them: local index 0 for a vertex, neighbour e of maxv for  */
+/* an edge, star triangle t for a triangle, star tet q for a tet.           */
+/* Returns -3 for a code that names no cell of the grid.                    */
+/* Pinned by: for vertices it is the sort by order (numpy argsort); a       */
+/* hand-worked 2x2x2 example (tests/golden/filtration_cube2.*) with ties    */
+/* broken at the second, third and fourth entries; the output is a         */
+/* permutation of the input with non-decreasing highest-vertex order        */
+/* (tests/test_oracle_filtration.py).                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { int64_t key[4]; int64_t code; } fcell_t;
+
+static int cmp_fcell(const void *pa, const void *pb)
+{
+    const fcell_t *a = (const fcell_t *)pa, *b = (const fcell_t *)pb;
+    for (int i = 0; i < 4; ++i)
+        if (a->key[i] != b->key[i]) return a->key[i] < b->key[i] ? -1 : 1;
+    return 0;
+}
+
+/* vertex id of neighbour e of v, or -1 outside the grid */
+static int64_t neighbour_of(const int64_t *dims, int64_t v, int e)
+{
+    int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    int64_t x = v % nx, y = (v / nx) % ny, z = v / (nx * ny);
+    int64_t a = x + NB[e][0], b = y + NB[e][1], c = z + NB[e][2];
+    if (a < 0 || b < 0 || c < 0 || a >= nx || b >= ny || c >= nz) return -1;
+    return a + nx * (b + ny * c);
+}
+
+int oracle_filtration_sort(const int32_t *order, const int64_t *dims, const int64_t *codes, int64_t n,
+                           int dim, int64_t *out)
+{
+    build_tables();
+    if (tables_built != 1) return -1;
+    if (dim < 0 || dim > 3) return -3;
+    int64_t nv = dims[0] * dims[1] * dims[2];
+    fcell_t *c = (fcell_t *)malloc(sizeof(fcell_t) * (size_t)(n > 0 ? n : 1));
+    if (!c) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t v = codes[i] >> 8;
+        int loc = (int)(codes[i] & 255);
+        int64_t vert[4] = {v, -1, -1, -1};
+        int others[3] = {-1, -1, -1};
+        if (v < 0 || v >= nv) { free(c); return -3; }
+        if (dim == 0 && loc != 0) { free(c); return -3; }
+        if (dim == 1) { if (loc >= 14) { free(c); return -3; } others[0] = loc; }
+        if (dim == 2) { if (loc >= 36) { free(c); return -3; } others[0] = TRI[loc][0]; others[1] = TRI[loc][1]; }
+        if (dim == 3) {
+            if (loc >= 24) { free(c); return -3; }
+            others[0] = TET[loc][0]; others[1] = TET[loc][1]; others[2] = TET[loc][2];
+        }
+        for (int k = 0; k < dim; ++k) {
+            vert[k + 1] = neighbour_of(dims, v, others[k]);
+            if (vert[k + 1] < 0) { free(c); return -3; }
+        }
+        for (int k = 0; k < 4; ++k) c[i].key[k] = k <= dim ? (int64_t)order[vert[k]] : -1;
+        sort_desc(c[i].key, dim + 1);
+        c[i].code = codes[i];
+    }
+    qsort(c, (size_t)n, sizeof(fcell_t), cmp_fcell);
+    for (int64_t i = 0; i < n; ++i) out[i] = c[i].code;
+    free(c);
+    return 0;
+}
