@@ -277,6 +277,20 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_values_gradient = ev0.elapsed_time(ev1) / 3
+    # the extracted lists in filtration order (Section 2.1; the local sort
+    # after extraction), all four dimensions; not part of the step
+    sorted_lists = [torch.empty_like(lists[d]) for d in range(4)]
+    for d in range(4):
+        dms.critical_sort(lists[d], d, order_t, dims, out=sorted_lists[d], flags=flags, check=False)
+    ev0.record(stream)
+    for _ in range(3):
+        for d in range(4):
+            dms.critical_sort(lists[d], d, order_t, dims, out=sorted_lists[d], flags=flags, check=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_critical_sort = ev0.elapsed_time(ev1) / 3
+    if int(flags.item()) != 0:
+        raise RuntimeError("device flags set: %d" % int(flags.item()))
     ms_step = wall / args.steps * 1e3
     value = owned / (ms_step / 1e3) / 1e9
 
@@ -308,6 +322,7 @@ def main():
                    "owned_vertices": owned, "critical_counts": [int(c) for c in cap]},
         "stage_ms": {k: round(v, 3) for k, v in ms.items()},
         "gradient_from_values_ms": round(ms_values_gradient, 3),
+        "critical_sort_ms": round(ms_critical_sort, 3),
         "stage_frac_hbm": {k: round(ALG_BYTES[k] * owned / (ms[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
                            for k in ms},
         "roofline": roofline,

@@ -51,7 +51,8 @@ typedef enum {
 /* bits OR-ed into *dev_flags by the device */
 enum {
     DMS_FLAG_NAN = 1u,      /* a NaN value: the order (and all that follows) is undefined */
-    DMS_FLAG_CAPACITY = 2u  /* a critical list exceeded its capacity; counts stay exact */
+    DMS_FLAG_CAPACITY = 2u, /* a critical list exceeded its capacity; counts stay exact */
+    DMS_FLAG_BADCODE = 4u   /* a cell code names no cell of the grid (dms_critical_sort) */
 };
 
 /* value types */
@@ -277,6 +278,27 @@ int dms_d0_triplets(const uint32_t *rec, const int32_t *order, const int64_t dim
 int dms_d0_pairs_sorted_host(const int64_t *tri_edge, const int32_t *tri_min0, const int32_t *tri_min1,
                              int64_t ntri, const int32_t *min_order, int64_t n0, int64_t *pair_edge,
                              int32_t *pair_min, int64_t capacity, int64_t *npairs);
+
+/* ----------------------------------------------------------------------------
+ * Critical cells in filtration order -- Section 2.1 (a cell's key is the list
+ * of its vertex orders sorted decreasingly; cells of one dimension compare by
+ * their keys lexicographically) and the local sort of the extracted lists
+ * (Section 3, Extract).
+ *
+ * codes [device, count]: cells of dimension dim (0..3) of the grid dims, as
+ * dms_critical_simplices writes them, (maxv << 8) | local index, in any
+ * order.  order [device]: the grid's order (dms_order).  sorted [device,
+ * count]: receives the same codes in increasing filtration order (unique:
+ * distinct cells have distinct keys); it must not overlap codes.
+ * workspace: dms_critical_sort_workspace_size(count) bytes.  A code naming no
+ * cell of the grid sets DMS_FLAG_BADCODE in *dev_flags (such cells sort last).
+ * Errors: DMS_E_ARG, DMS_E_SIZE (count above 2^31 - 1), DMS_E_WORKSPACE,
+ * DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+size_t dms_critical_sort_workspace_size(int64_t count);
+int dms_critical_sort(const int64_t *codes, int64_t count, int dim, const int32_t *order,
+                      const int64_t dims[3], int64_t *sorted, void *workspace, size_t workspace_bytes,
+                      uint32_t *dev_flags, void *stream);
 
 #ifdef __cplusplus
 }

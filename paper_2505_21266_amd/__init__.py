@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdms.so")
 
 DMS_F32, DMS_F64 = 0, 1
-FLAG_NAN, FLAG_CAPACITY = 1, 2
+FLAG_NAN, FLAG_CAPACITY, FLAG_BADCODE = 1, 2, 4
 STATUS = {0: "DMS_OK", 1: "DMS_E_ARG", 2: "DMS_E_SIZE", 3: "DMS_E_WORKSPACE",
           4: "DMS_E_UNSUPPORTED", 5: "DMS_E_HIP"}
 
@@ -29,7 +29,7 @@ SYMBOLS = ("dms_status_str", "dms_version", "dms_star_tables", "dms_order_worksp
            "dms_critical_simplices", "dms_gradient_backward", "dms_d0_pairs_host",
            "dms_batch_create", "dms_batch_workspace_size", "dms_batch_total", "dms_batch_variant",
            "dms_batch_run", "dms_batch_destroy", "dms_d0_workspace_size", "dms_d0_triplets",
-           "dms_d0_pairs_sorted_host")
+           "dms_d0_pairs_sorted_host", "dms_critical_sort_workspace_size", "dms_critical_sort")
 
 _lib = None
 
@@ -80,8 +80,11 @@ def lib():
     L.dms_d0_workspace_size.restype = SZ
     L.dms_d0_triplets.argtypes = [P, P, P, P, I64, P, I64, P, P, P, P, P, P, SZ, P, P]
     L.dms_d0_pairs_sorted_host.argtypes = [P, P, P, I64, P, I64, P, P, I64, P]
+    L.dms_critical_sort_workspace_size.argtypes = [I64]
+    L.dms_critical_sort_workspace_size.restype = SZ
+    L.dms_critical_sort.argtypes = [P, I64, ctypes.c_int, P, P, P, P, SZ, P, P]
     for f in ("dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_discrete_gradient_values",
-              "dms_critical_simplices", "dms_d0_triplets", "dms_d0_pairs_sorted_host",
+              "dms_critical_simplices", "dms_d0_triplets", "dms_d0_pairs_sorted_host", "dms_critical_sort",
               "dms_gradient_backward", "dms_d0_pairs_host", "dms_batch_create", "dms_batch_variant",
               "dms_batch_run"):
         getattr(L, f).restype = I
@@ -169,6 +172,8 @@ def check_flags(flags, allow=0):
         raise ValueError("NaN in the input field")
     if f & ~allow & FLAG_CAPACITY:
         raise RuntimeError("critical list capacity exceeded")
+    if f & ~allow & FLAG_BADCODE:
+        raise ValueError("a cell code names no cell of the grid")
     return f
 
 
@@ -366,6 +371,30 @@ def d0_pairs_host(rec_np, order_np, dims, crit1_np):
            "dms_d0_pairs_host")
     k = int(npairs[0])
     return pe[:k], pm[:k]
+
+
+def critical_sort(codes, dim, order_t, dims, out=None, flags=None, check=True):
+    """Critical cells of dimension dim (int64 device codes, as
+    critical_simplices lists them) in the filtration order of Section 2.1
+    (dms_critical_sort).  Returns a new int64 tensor unless out is given."""
+    import torch
+    L = lib()
+    n = int(codes.numel())
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=codes.device)
+    if n == 0:
+        return out
+    codes = codes.contiguous()
+    if flags is None:
+        flags = new_flags(codes.device)
+    d, dp = _arr3(dims)
+    ws = torch.empty(max(int(L.dms_critical_sort_workspace_size(n)), 256), dtype=torch.uint8,
+                     device=codes.device)
+    _check(L.dms_critical_sort(_ptr(codes), n, int(dim), _ptr(order_t), dp, _ptr(out), _ptr(ws), ws.numel(),
+                               _ptr(flags), _stream(codes)), "dms_critical_sort")
+    if check:
+        check_flags(flags)
+    return out
 
 
 def d0_pairs(rec, order_t, dims, crit0, crit1):

@@ -375,6 +375,55 @@ def test_d0_pairs_gpu_matches_oracle(shape, kind, seed):
     assert len(pe) == len(crit[0]) - 1  # every minimum but one dies (one component)
 
 
+@pytest.mark.parametrize("shape,kind,seed", [((24, 20, 16), "noise", 71), ((32, 32, 32), "f64", 72),
+                                             ((18, 30, 9), "ties", 73), ((40, 1, 7), "noise", 74),
+                                             ((33, 17, 65), "mixture", 75), ((96, 96, 96), "noise", 76)])
+def test_critical_sort_matches_oracle(shape, kind, seed):
+    """Critical lists of every dimension in filtration order (Section 2.1),
+    from a scrambled input order, bit-exact against the oracle."""
+    nz, ny, nx = shape
+    v = _field((nx, ny, nz), kind, seed)
+    dims = (nx, ny, nz)
+    o = oracle.order(v)
+    rec, _, _ = oracle.lower_stars(o, dims)
+    crit, _ = oracle.critical_simplices(rec, dims)
+    _say("critical sort", shape, kind, [len(c) for c in crit])
+    og = dms.order(_dev(v))
+    rg = dms.discrete_gradient(og)
+    lists, counts = dms.critical_simplices(rg, dims)
+    prng = np.random.default_rng(seed)
+    for d in range(4):
+        c = np.asarray(crit[d], np.int64)
+        assert (lists[d].cpu().numpy() == c).all()
+        p = prng.permutation(c.size)
+        want = oracle.filtration_sort(o, dims, c[p], d)
+        got = dms.critical_sort(lists[d][_dev(p)], d, og, dims).cpu().numpy()
+        assert (got == want).all(), d
+
+
+def test_critical_sort_edge_cases():
+    dims = (9, 8, 7)
+    v = _field(dims, "noise", 81)
+    o = oracle.order(v)
+    og = dms.order(_dev(v))
+    empty = torch.empty(0, dtype=torch.int64, device="cuda")
+    assert dms.critical_sort(empty, 2, og, dims).numel() == 0
+    one = _dev(np.array([(5 << 8) | 0], np.int64))
+    assert dms.critical_sort(one, 0, og, dims).cpu().tolist() == [5 << 8]
+    # every vertex (a long list through all radix passes) against the oracle
+    n = 9 * 8 * 7
+    ids = np.random.default_rng(82).permutation(n).astype(np.int64) << 8
+    got = dms.critical_sort(_dev(ids), 0, og, dims).cpu().numpy()
+    assert (got == oracle.filtration_sort(o, dims, ids, 0)).all()
+    # a code that names no cell: flagged, no fault
+    bad = _dev(np.array([(3 << 8) | 1, (4 << 8) | 40], np.int64))
+    with pytest.raises(ValueError):
+        dms.critical_sort(bad, 2, og, dims)
+    corner = _dev(np.array([((n - 1) << 8) | 13], np.int64))  # neighbour +(1,1,1) of the last vertex
+    with pytest.raises(ValueError):
+        dms.critical_sort(corner, 1, og, dims)
+
+
 def test_backward_kernel_runs():
     # several deaths on one vertex, given adjacent: summed in pair order
     bc = _dev(np.array([5 << 8, 9 << 8, 11 << 8], np.int64))

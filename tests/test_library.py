@@ -155,3 +155,23 @@ def test_d0_pairs_sorted_host_hand_case():
                                       mo.ctypes.data_as(P), 3, pe.ctypes.data_as(P), pm.ctypes.data_as(P),
                                       3, npairs.ctypes.data_as(P)) == 1
 
+
+
+def test_critical_sort_argument_errors(L):
+    P = ctypes.c_void_p
+    fake, other = P(4096), P(8192)  # never dereferenced: every call below fails its checks first
+    d, dp = _a3([4, 4, 4])
+    z, zp = _a3([0, 4, 4])
+    big, bigp = _a3([2048, 2048, 1024])
+    ws = L.dms_critical_sort_workspace_size(100)
+    assert ws >= 100 * 36
+    assert L.dms_critical_sort_workspace_size(-1) == 0
+    assert L.dms_critical_sort(fake, 10, 4, fake, dp, other, fake, ws, fake, None) == 1  # dim
+    assert L.dms_critical_sort(fake, 10, -1, fake, dp, other, fake, ws, fake, None) == 1
+    assert L.dms_critical_sort(fake, 10, 1, fake, zp, other, fake, ws, fake, None) == 1  # dims
+    assert L.dms_critical_sort(fake, -1, 1, fake, dp, other, fake, ws, fake, None) == 1
+    assert L.dms_critical_sort(None, 10, 1, fake, dp, other, fake, ws, fake, None) == 1
+    assert L.dms_critical_sort(fake, 10, 1, fake, dp, fake, fake, ws, fake, None) == 1  # in place
+    assert L.dms_critical_sort(fake, 10, 1, fake, bigp, other, fake, ws, fake, None) == 2
+    assert L.dms_critical_sort(fake, 100, 1, fake, dp, other, fake, 16, fake, None) == 3
+    assert L.dms_critical_sort(None, 0, 1, None, dp, None, None, 0, None, None) == 0  # empty list
