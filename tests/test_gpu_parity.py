@@ -137,6 +137,61 @@ def test_order_config1():
     assert (got == oracle.order(v)).all()
 
 
+def _critical_codes_of(rec4, v):
+    """Critical cells of one decoded record as (dimension, code) pairs."""
+    st = oracle.decode_record(rec4)
+    out = []
+    for c in np.nonzero(st == oracle.ST_CRIT)[0]:
+        c = int(c)
+        if c == oracle.CELL_X:
+            out.append((0, v << 8))
+        elif c < oracle.CELL_TRI0:
+            out.append((1, (v << 8) | (c - oracle.CELL_EDGE0)))
+        elif c < oracle.CELL_TET0:
+            out.append((2, (v << 8) | (c - oracle.CELL_TRI0)))
+        else:
+            out.append((3, (v << 8) | (c - oracle.CELL_TET0)))
+    return out
+
+
+def test_gradient_full_block_sampled():
+    """The 1024^3-owned workload in the launch configuration the benchmark
+    times (GPU order of the 1026^3 block, records of the owned box, the
+    queue): 60000 sampled owned vertices have the oracle's records (computed
+    from the values), and the critical lists restricted to the sampled
+    vertices are exactly the critical cells of those records."""
+    v, lo, hi = inputs.config3()
+    nz, ny, nx = v.shape
+    dims = (nx, ny, nz)
+    w = [hi[i] - lo[i] for i in range(3)]
+    rng = np.random.default_rng(31)
+    m = 60000
+    bx, by, bz = (rng.integers(0, w[i], m) for i in range(3))
+    vids = (bx + lo[0]) + nx * ((by + lo[1]) + ny * (bz + lo[2]))
+    box_idx = bx + w[0] * (by + w[1] * bz)
+    want = oracle.lower_stars_sampled(v, dims, vids)
+    _say("full block sampled", v.shape, m)
+    vt = _dev(v)
+    del v
+    o = dms.order(vt)
+    del vt
+    rec = dms.discrete_gradient(o, lo, hi, workspace=dms.gradient_workspace(o, lo, hi))
+    got = rec[_dev(box_idx)].cpu().numpy().view(np.uint32)
+    assert (got == want).all()
+    lists, counts = dms.critical_simplices(rec, dims, lo, hi)
+    sample = set(int(x) for x in vids)
+    expect = [set() for _ in range(4)]
+    for r4, x in zip(want, vids):
+        for d, code in _critical_codes_of(r4, int(x)):
+            expect[d].add(code)
+    for d in range(4):
+        c = lists[d].cpu().numpy()
+        mine = set(int(x) for x in c[np.isin(c >> 8, vids)])
+        assert mine == expect[d], d
+    assert sum(len(e) for e in expect) > 50  # the sample reaches critical cells
+    del rec, o
+
+
 # -------------------------------------------------------------- gradient
 
 GRAD_CASES = [
@@ -327,11 +382,17 @@ def test_determinism_double_run():
 
 # -------------------------------------------------------------- backward
 
-@pytest.mark.parametrize("shape", [(20, 22, 24), (32, 32, 32)])
+@pytest.mark.parametrize("shape", [(20, 22, 24), (32, 32, 32), "config5"])
 def test_backward_matches_oracle(shape):
+    """Pairs, loss and gradient of the differentiable form against the
+    oracle; "config5" is the full 128^3 float64 workload."""
+    if shape == "config5":
+        f = inputs.config5()
+        shape = f.shape
+    else:
+        rng = np.random.default_rng(41)
+        f = inputs.min_gap_pass(inputs.mixture_field(shape, 6, rng, 1e-4, np.float64))
     nz, ny, nx = shape
-    rng = np.random.default_rng(41)
-    f = inputs.min_gap_pass(inputs.mixture_field(shape, 6, rng, 1e-4, np.float64))
     dims = (nx, ny, nz)
     o = oracle.order(f)
     rec, _, _ = oracle.lower_stars(o, dims)
@@ -346,7 +407,7 @@ def test_backward_matches_oracle(shape):
     loss = d0_loss(births, deaths, 0.05)
     loss.backward()
     g = x.grad.cpu().numpy().reshape(-1)
-    assert abs(float(loss) - loss_o) <= 1e-12 * max(1.0, abs(loss_o))
+    assert abs(float(loss.detach()) - loss_o) <= 1e-12 * max(1.0, abs(loss_o))
     scale = np.abs(grad_o).max()
     assert np.all(np.abs(g - grad_o) <= 1e-10 * np.maximum(np.abs(grad_o), 1e-300) + 1e-300)
     assert scale > 0
