@@ -19,6 +19,7 @@ Functions:
   d0_pairs(...)              Algorithm 1 on the extremum graph
   d0_loss_grad(...)          loss of the differentiable form and its gradient
   filtration_sort(...)       critical cells of one dimension in filtration order
+  d2_pairs(...)              the dual of Algorithm 1: 2-saddle / maximum pairs
 """
 import ctypes
 import os
@@ -68,10 +69,11 @@ def _load():
     lib.oracle_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P]
     lib.oracle_d0_pairs.argtypes = [P, P, P, P, I64, P, P, P]
     lib.oracle_filtration_sort.argtypes = [P, P, P, I64, I, P]
+    lib.oracle_d2_pairs.argtypes = [P, P, P, P, I64, P, I64, P, P, P]
     for f in (lib.oracle_star_tables, lib.oracle_order_f32, lib.oracle_order_f64,
               lib.oracle_pls_local, lib.oracle_lower_stars, lib.oracle_lower_stars_sampled,
               lib.oracle_decode_record, lib.oracle_critical_simplices, lib.oracle_d0_pairs,
-              lib.oracle_filtration_sort):
+              lib.oracle_filtration_sort, lib.oracle_d2_pairs):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -259,3 +261,23 @@ def filtration_sort(order_arr, dims, codes, dim):
     if rc != 0:
         raise ValueError("oracle filtration sort failed (%d)" % rc)
     return out[:c.size].copy()
+
+
+def d2_pairs(order_arr, rec_full, dims, crit2, crit3):
+    """D2 pairs (the dual of Algorithm 1 on the tets, Section 2.6) over the
+    whole grid.  Returns (pair_tri codes, pair_tet codes) in visiting order
+    (decreasing triangle)."""
+    lib = _load()
+    o = np.ascontiguousarray(order_arr, dtype=np.int32).reshape(-1)
+    r = np.ascontiguousarray(rec_full, dtype=np.uint32)
+    c2 = _i64(crit2).reshape(-1)
+    c3 = _i64(crit3).reshape(-1)
+    pt = np.zeros(max(c2.size, 1), np.int64)
+    pq = np.zeros(max(c2.size, 1), np.int64)
+    npairs = np.zeros(1, np.int64)
+    rc = lib.oracle_d2_pairs(_p(o), _p(r), _p(_i64(dims)), _p(c2), c2.size, _p(c3), c3.size, _p(pt), _p(pq),
+                             _p(npairs))
+    if rc != 0:
+        raise RuntimeError("oracle d2 failed (%d)" % rc)
+    n = int(npairs[0])
+    return pt[:n].copy(), pq[:n].copy()

@@ -860,3 +860,209 @@ int oracle_filtration_sort(const int32_t *order, const int64_t *dims, const int6
     free(c);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* O-8  D2 pairing from the gradient (Section 2.6: D2 is computed like D0,   */
+/* on the dual complex, where every discrete vector is reversed).  Reading: */
+/* the dual graph has one node per tet plus one node for the outside of the */
+/* grid; two tets sharing a triangle are adjacent, and a triangle on the    */
+/* grid boundary joins its one tet to the outside node.                     */
+/*   - A tet that is the head of a gradient pair (triangle s, tet) is left  */
+/*     through s to the other tet containing s (the outside node if s is on */
+/*     the boundary); a critical tet ends the walk (a maximum).             */
+/*   - For each critical triangle sigma, walk from each of its cofacet tets */
+/*     (the outside node for a missing one): t0, t1.  Keep (sigma, t0, t1)  */
+/*     if t0 != t1.                                                         */
+/*   - Visit the kept triplets in decreasing order of sigma (Section 2.1    */
+/*     comparison).  r0, r1 = representatives of t0, t1; if they differ,    */
+/*     make r0 the lower one (tets compared as in Section 2.1, the outside  */
+/*     node above every tet), pair (sigma, r0), and set the representative  */
+/*     of r0 and of t0 to r1.                                               */
+/* Codes are (max vertex << 8) | local index, as O-5 writes them.           */
+/* Pinned by: equality with the (triangle, tet) pairs of non-zero            */
+/* persistence of a mod-2 boundary-matrix reduction of the lexicographic    */
+/* filtration (tests/brute.py) on small grids; #pairs = c3 (every maximum   */
+/* dies: the grid is a ball); empty on flat grids (tests/test_oracle_d2.py).*/
+/* ------------------------------------------------------------------------ */
+
+#define D2_OUTSIDE (-1)
+
+/* neighbour index e with to = from + NB[e], or -1 */
+static int nb_index(const int64_t *dims, int64_t from, int64_t to)
+{
+    for (int e = 0; e < 14; ++e)
+        if (neighbour_of(dims, from, e) == to) return e;
+    return -1;
+}
+
+static int64_t cell_code_of(const int32_t *order, const int64_t *dims, const int64_t *vs, int k)
+{
+    int m = 0;
+    for (int i = 1; i < k; ++i)
+        if (order[vs[i]] > order[vs[m]]) m = i;
+    int es[3], ne = 0;
+    for (int i = 0; i < k; ++i)
+        if (i != m) es[ne++] = nb_index(dims, vs[m], vs[i]);
+    for (int i = 0; i < ne; ++i)
+        for (int j = i + 1; j < ne; ++j)
+            if (es[j] < es[i]) { int t = es[i]; es[i] = es[j]; es[j] = t; }
+    int loc = -1;
+    if (k == 3) loc = TRI_ID[es[0]][es[1]];
+    if (k == 4)
+        for (int q = 0; q < 24; ++q)
+            if (TET[q][0] == es[0] && TET[q][1] == es[1] && TET[q][2] == es[2]) loc = q;
+    return (vs[m] << 8) | loc;
+}
+
+static void cell_vertices(const int64_t *dims, int64_t code, int k, int64_t *vs)
+{
+    int64_t v = code >> 8;
+    int loc = (int)(code & 255);
+    vs[0] = v;
+    if (k == 3) { vs[1] = neighbour_of(dims, v, TRI[loc][0]); vs[2] = neighbour_of(dims, v, TRI[loc][1]); }
+    if (k == 4)
+        for (int i = 0; i < 3; ++i) vs[i + 1] = neighbour_of(dims, v, TET[loc][i]);
+}
+
+/* fourth vertices d of the tets containing triangle {a, b, c}, other than
+ * `skip`; returns how many (at most 2) */
+static int tri_cofacets(const int64_t *dims, const int64_t *abc, int64_t skip, int64_t *d)
+{
+    int n = 0;
+    for (int e = 0; e < 14; ++e) {
+        int64_t x = neighbour_of(dims, abc[0], e);
+        if (x < 0 || x == abc[1] || x == abc[2] || x == skip) continue;
+        if (nb_index(dims, abc[1], x) < 0 || nb_index(dims, abc[2], x) < 0) continue;
+        if (n < 2) d[n] = x;
+        ++n;
+    }
+    return n;
+}
+
+static int tri_state(const uint32_t *rec, int64_t v, int t)
+{
+    int b = 56 + 2 * t;
+    return (int)((rec[4 * v + b / 32] >> (b % 32)) & 3u);
+}
+
+/* the maximum reached from tet `code`, or D2_OUTSIDE */
+static int64_t ascend(const int32_t *order, const uint32_t *rec, const int64_t *dims, int64_t code)
+{
+    for (;;) {
+        int64_t m = code >> 8;
+        int q = (int)(code & 255);
+        int tail = -1;
+        for (int s = 0; s < 3; ++s) {
+            int t = TET_TRIS[q][s];
+            int g = tri_state(rec, m, t);
+            if (g && TRI_TETS[t][g - 1] == q) tail = t;
+        }
+        if (tail < 0) return code; /* critical tet */
+        int64_t tv[4], abc[3], d[2];
+        cell_vertices(dims, code, 4, tv);
+        abc[0] = m;
+        abc[1] = neighbour_of(dims, m, TRI[tail][0]);
+        abc[2] = neighbour_of(dims, m, TRI[tail][1]);
+        int64_t fourth = -1;
+        for (int i = 1; i < 4; ++i)
+            if (tv[i] != abc[1] && tv[i] != abc[2]) fourth = tv[i];
+        if (tri_cofacets(dims, abc, fourth, d) == 0) return D2_OUTSIDE;
+        int64_t nv[4] = {abc[0], abc[1], abc[2], d[0]};
+        code = cell_code_of(order, dims, nv, 4);
+    }
+}
+
+typedef struct { int64_t key[3]; int64_t sigma, t0, t1; } trip2_t;
+
+static int cmp_trip2_desc(const void *pa, const void *pb)
+{
+    const trip2_t *a = (const trip2_t *)pa, *b = (const trip2_t *)pb;
+    for (int i = 0; i < 3; ++i)
+        if (a->key[i] != b->key[i]) return a->key[i] > b->key[i] ? -1 : 1;
+    return 0;
+}
+
+static int cmp_i64(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    return a < b ? -1 : a > b;
+}
+
+/* index of a maximum in the sorted list of critical tets; n3 for outside */
+static int64_t max_index(const int64_t *sorted3, int64_t n3, int64_t code)
+{
+    if (code == D2_OUTSIDE) return n3;
+    const int64_t *p = (const int64_t *)bsearch(&code, sorted3, (size_t)n3, sizeof(int64_t), cmp_i64);
+    return p ? (int64_t)(p - sorted3) : -1;
+}
+
+/* Section 2.1 comparison of two maxima by index (n3 = the outside node) */
+static int max_lower(const int32_t *order, const int64_t *dims, const int64_t *sorted3, int64_t n3,
+                     int64_t a, int64_t b)
+{
+    if (a == n3) return 0;
+    if (b == n3) return 1;
+    int64_t va[4], vb[4], ka[4], kb[4];
+    cell_vertices(dims, sorted3[a], 4, va);
+    cell_vertices(dims, sorted3[b], 4, vb);
+    for (int i = 0; i < 4; ++i) { ka[i] = order[va[i]]; kb[i] = order[vb[i]]; }
+    sort_desc(ka, 4);
+    sort_desc(kb, 4);
+    for (int i = 0; i < 4; ++i)
+        if (ka[i] != kb[i]) return ka[i] < kb[i];
+    return 0;
+}
+
+int oracle_d2_pairs(const int32_t *order, const uint32_t *rec, const int64_t *dims, const int64_t *crit2,
+                    int64_t n2, const int64_t *crit3, int64_t n3, int64_t *pair_tri, int64_t *pair_tet,
+                    int64_t *npairs)
+{
+    build_tables();
+    if (tables_built != 1) return -1;
+    trip2_t *tr = (trip2_t *)malloc(sizeof(trip2_t) * (size_t)(n2 > 0 ? n2 : 1));
+    int64_t *s3 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n3 > 0 ? n3 : 1));
+    int64_t *rep = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n3 + 1));
+    if (!tr || !s3 || !rep) { free(tr); free(s3); free(rep); return -2; }
+    for (int64_t i = 0; i < n3; ++i) s3[i] = crit3[i];
+    qsort(s3, (size_t)n3, sizeof(int64_t), cmp_i64);
+    int64_t nt = 0;
+    for (int64_t s = 0; s < n2; ++s) {
+        int64_t abc[3], d[2], t[2] = {D2_OUTSIDE, D2_OUTSIDE};
+        cell_vertices(dims, crit2[s], 3, abc);
+        int nc = tri_cofacets(dims, abc, -1, d);
+        for (int c = 0; c < nc && c < 2; ++c) {
+            int64_t tv[4] = {abc[0], abc[1], abc[2], d[c]};
+            t[c] = ascend(order, rec, dims, cell_code_of(order, dims, tv, 4));
+        }
+        int64_t i0 = max_index(s3, n3, t[0]), i1 = max_index(s3, n3, t[1]);
+        if (i0 < 0 || i1 < 0) { free(tr); free(s3); free(rep); return -3; }
+        if (i0 == i1) continue;
+        int64_t k[3] = {order[abc[0]], order[abc[1]], order[abc[2]]};
+        sort_desc(k, 3);
+        for (int i = 0; i < 3; ++i) tr[nt].key[i] = k[i];
+        tr[nt].sigma = crit2[s];
+        tr[nt].t0 = i0;
+        tr[nt].t1 = i1;
+        ++nt;
+    }
+    qsort(tr, (size_t)nt, sizeof(trip2_t), cmp_trip2_desc);
+    for (int64_t i = 0; i <= n3; ++i) rep[i] = i;
+    int64_t np = 0;
+    for (int64_t s = 0; s < nt; ++s) {
+        int64_t r0 = tr[s].t0, r1 = tr[s].t1;
+        while (rep[r0] != r0) r0 = rep[r0];
+        while (rep[r1] != r1) r1 = rep[r1];
+        if (r0 == r1) continue;
+        if (max_lower(order, dims, s3, n3, r1, r0)) { int64_t x = r0; r0 = r1; r1 = x; }
+        pair_tri[np] = tr[s].sigma;
+        pair_tet[np] = s3[r0];
+        ++np;
+        rep[r0] = r1;
+        rep[tr[s].t0] = r1;
+    }
+    *npairs = np;
+    free(tr);
+    free(s3);
+    free(rep);
+    return 0;
+}
