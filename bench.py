@@ -146,8 +146,9 @@ def bench_batched(dev, reps):
 def bench_differentiable(dev, reps):
     """128^3 float64 field (16 Gaussians + 1e-4 noise, min gap 1e-9): GPU
     forward (order, gradient, extraction), D0 pairing (extremum graph on the
-    GPU, union-find on the host), GPU backward.  The all-host pairing is
-    timed beside it for comparison."""
+    GPU, union-find on the host), GPU backward.  The all-host D0 pairing is
+    timed beside it for comparison, and the D2 pairing (ascents on the dual
+    complex on the GPU, union-find on the host) after it."""
     import torch
 
     import paper_2505_21266_amd as dms
@@ -161,7 +162,7 @@ def bench_differentiable(dev, reps):
     lists, counts = dms.critical_simplices(rec, dims)
     cap = counts.cpu().numpy()
     torch.cuda.synchronize()
-    fwd, host, bwd, allhost = [], [], [], []
+    fwd, host, bwd, allhost, d2 = [], [], [], [], []
     for _ in range(reps):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         e[0].record()
@@ -179,6 +180,9 @@ def bench_differentiable(dev, reps):
         allhost.append((time.perf_counter() - t2) * 1e3)
         if not ((pe2 == pe).all() and (pm2 == pm).all()):
             raise RuntimeError("D0 pairings disagree")
+        t3 = time.perf_counter()
+        pt, pq = dms.d2_pairs(rec, o, dims, lists[2], lists[3])
+        d2.append((time.perf_counter() - t3) * 1e3)
         dc = torch.from_numpy(pe).to(dev)
         bc = torch.from_numpy(pm).to(dev) << 8
         flat = x.reshape(-1)
@@ -196,6 +200,7 @@ def bench_differentiable(dev, reps):
     return {"vertices": n, "pairs": int(pe.size), "forward_gpu_ms": round(float(np.median(fwd)), 3),
             "d0_ms": round(float(np.median(host)), 3),
             "d0_all_host_ms": round(float(np.median(allhost)), 3),
+            "d2_pairs": int(pt.size), "d2_ms": round(float(np.median(d2)), 3),
             "backward_gpu_ms": round(float(np.median(bwd)), 4), "reps": reps}
 
 

@@ -300,6 +300,48 @@ int dms_critical_sort(const int64_t *codes, int64_t count, int dim, const int32_
                       const int64_t dims[3], int64_t *sorted, void *workspace, size_t workspace_bytes,
                       uint32_t *dev_flags, void *stream);
 
+/* ----------------------------------------------------------------------------
+ * D2 pairing on the GPU, extremum-graph half -- Section 2.6 (D2 is computed
+ * like D0 on the dual complex, where every discrete vector is reversed).  The
+ * dual graph has one node per tet and one for the outside of the grid; a
+ * triangle on the grid boundary joins its one tet to the outside node.  From
+ * the two cofacet tets of each critical triangle the dual v-path is followed
+ * (a tet that is the head of a gradient pair continues through its tail
+ * triangle into the other tet containing it) to a critical tet or the outside.
+ *
+ * rec: the records of the WHOLE grid; order: the grid's order; crit2 / crit3:
+ * its critical triangle and tet codes as dms_critical_simplices lists them
+ * (crit3 in increasing code order).  All device arrays.
+ * Outputs (device): tri_code, tri_max0, tri_max1 [capacity n2]: the triplets
+ * whose two maxima differ, by DECREASING triangle (Section 2.1 order);
+ * tri_max* are indices into crit3, n3 standing for the outside node;
+ * max_rank[n3]: the place of each critical tet in the Section 2.1 order of
+ * crit3; *ntri: the number of triplets (int64).
+ * workspace: dms_d2_workspace_size(n2, n3) bytes.  A maximum missing from
+ * crit3 (a truncated list) or a bad code sets DMS_FLAG_CAPACITY.
+ * Errors: DMS_E_ARG, DMS_E_SIZE, DMS_E_WORKSPACE, DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+size_t dms_d2_workspace_size(int64_t n2, int64_t n3);
+int dms_d2_triplets(const uint32_t *rec, const int32_t *order, const int64_t dims[3],
+                    const int64_t *crit2, int64_t n2, const int64_t *crit3, int64_t n3,
+                    int64_t *tri_code, int32_t *tri_max0, int32_t *tri_max1, int32_t *max_rank,
+                    int64_t *ntri, void *workspace, size_t workspace_bytes, uint32_t *dev_flags,
+                    void *stream);
+
+/* ----------------------------------------------------------------------------
+ * D2 pairing, union-find half -- the dual of Algorithm 1 over the triplets
+ * of dms_d2_triplets, on [host] arrays, in their (decreasing) order: each
+ * triplet joins the classes of its maxima; the lower representative (smaller
+ * max_rank; index n3, the outside node, is above every tet) dies at the
+ * triangle.  Outputs pair_tri (triangle codes) and pair_max (indices into
+ * crit3) in visiting order, up to capacity; *npairs is the exact count.
+ * Errors: DMS_E_ARG (bad arguments or a maximum index outside [0, n3]),
+ * DMS_E_WORKSPACE (more pairs than capacity; npairs is still exact).
+ * -------------------------------------------------------------------------- */
+int dms_d2_pairs_sorted_host(const int64_t *tri_code, const int32_t *tri_max0, const int32_t *tri_max1,
+                             int64_t ntri, const int32_t *max_rank, int64_t n3, int64_t *pair_tri,
+                             int32_t *pair_max, int64_t capacity, int64_t *npairs);
+
 #ifdef __cplusplus
 }
 #endif

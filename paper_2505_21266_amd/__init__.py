@@ -29,7 +29,8 @@ SYMBOLS = ("dms_status_str", "dms_version", "dms_star_tables", "dms_order_worksp
            "dms_critical_simplices", "dms_gradient_backward", "dms_d0_pairs_host",
            "dms_batch_create", "dms_batch_workspace_size", "dms_batch_total", "dms_batch_variant",
            "dms_batch_run", "dms_batch_destroy", "dms_d0_workspace_size", "dms_d0_triplets",
-           "dms_d0_pairs_sorted_host", "dms_critical_sort_workspace_size", "dms_critical_sort")
+           "dms_d0_pairs_sorted_host", "dms_critical_sort_workspace_size", "dms_critical_sort",
+           "dms_d2_workspace_size", "dms_d2_triplets", "dms_d2_pairs_sorted_host")
 
 _lib = None
 
@@ -83,8 +84,13 @@ def lib():
     L.dms_critical_sort_workspace_size.argtypes = [I64]
     L.dms_critical_sort_workspace_size.restype = SZ
     L.dms_critical_sort.argtypes = [P, I64, ctypes.c_int, P, P, P, P, SZ, P, P]
+    L.dms_d2_workspace_size.argtypes = [I64, I64]
+    L.dms_d2_workspace_size.restype = SZ
+    L.dms_d2_triplets.argtypes = [P, P, P, P, I64, P, I64, P, P, P, P, P, P, SZ, P, P]
+    L.dms_d2_pairs_sorted_host.argtypes = [P, P, P, I64, P, I64, P, P, I64, P]
     for f in ("dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_discrete_gradient_values",
               "dms_critical_simplices", "dms_d0_triplets", "dms_d0_pairs_sorted_host", "dms_critical_sort",
+              "dms_d2_triplets", "dms_d2_pairs_sorted_host",
               "dms_gradient_backward", "dms_d0_pairs_host", "dms_batch_create", "dms_batch_variant",
               "dms_batch_run"):
         getattr(L, f).restype = I
@@ -438,6 +444,48 @@ def d0_pairs(rec, order_t, dims, crit0, crit1):
     return pe[:m], (c0[pm[:m]] >> 8).astype(np.int64)
 
 
+def d2_pairs(rec, order_t, dims, crit2, crit3):
+    """D2 pairing: ascents on the dual complex on the GPU (dms_d2_triplets:
+    triplets by decreasing triangle, maxima ranked in filtration order), the
+    union-find on the host (dms_d2_pairs_sorted_host).  rec/order_t/crit2/
+    crit3 are device tensors of the whole grid.  Returns numpy (pair_tri
+    codes, pair_tet codes)."""
+    import torch
+    L = lib()
+    P = ctypes.c_void_p
+    dev = rec.device
+    n2, n3 = int(crit2.numel()), int(crit3.numel())
+    d, dp = _arr3(dims)
+    tri_code = torch.empty(max(n2, 1), dtype=torch.int64, device=dev)
+    tri_max0 = torch.empty(max(n2, 1), dtype=torch.int32, device=dev)
+    tri_max1 = torch.empty(max(n2, 1), dtype=torch.int32, device=dev)
+    max_rank = torch.empty(max(n3, 1), dtype=torch.int32, device=dev)
+    ntri = torch.zeros(1, dtype=torch.int64, device=dev)
+    flags = new_flags(dev)
+    ws = torch.empty(max(int(L.dms_d2_workspace_size(n2, n3)), 256), dtype=torch.uint8, device=dev)
+    _check(L.dms_d2_triplets(_ptr(rec), _ptr(order_t), dp, _ptr(crit2), n2, _ptr(crit3), n3,
+                             _ptr(tri_code), _ptr(tri_max0), _ptr(tri_max1), _ptr(max_rank),
+                             _ptr(ntri), _ptr(ws), ws.numel(), _ptr(flags), _stream(rec)),
+           "dms_d2_triplets")
+    check_flags(flags)
+    k = int(ntri.item())
+    tc = np.ascontiguousarray(tri_code[:k].cpu().numpy())
+    t0 = np.ascontiguousarray(tri_max0[:k].cpu().numpy())
+    t1 = np.ascontiguousarray(tri_max1[:k].cpu().numpy())
+    mr = np.ascontiguousarray(max_rank[:n3].cpu().numpy())
+    c3 = crit3.cpu().numpy()
+    cap = max(k, 1)
+    pt = np.zeros(cap, np.int64)
+    pm = np.zeros(cap, np.int32)
+    npairs = np.zeros(1, np.int64)
+    _check(L.dms_d2_pairs_sorted_host(tc.ctypes.data_as(P), t0.ctypes.data_as(P), t1.ctypes.data_as(P),
+                                      k, mr.ctypes.data_as(P), n3, pt.ctypes.data_as(P),
+                                      pm.ctypes.data_as(P), cap, npairs.ctypes.data_as(P)),
+           "dms_d2_pairs_sorted_host")
+    m = int(npairs[0])
+    return pt[:m], c3[pm[:m]].astype(np.int64)
+
+
 def gradient_pipeline(values, lo=None, hi=None, cap=None):
     """order -> discrete gradient -> critical simplices for one field."""
     o = order(values)
@@ -527,4 +575,4 @@ class Batch:
             pass
 
 
-from .autograd import PersistenceD0  # noqa: E402  (torch autograd wrapper)
+from .autograd import PersistenceD0, PersistenceD2  # noqa: E402  (torch autograd wrapper)

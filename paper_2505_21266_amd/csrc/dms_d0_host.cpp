@@ -133,3 +133,46 @@ extern "C" int dms_d0_pairs_sorted_host(const int64_t *tri_edge, const int32_t *
     return np > capacity ? DMS_E_WORKSPACE : DMS_OK;
 }
 
+
+// The dual of Algorithm 1 for D2, over the triplets of dms_d2_triplets in
+// decreasing triangle order: each triplet joins the classes of its maxima;
+// the lower representative (smaller filtration rank; the outside node, index
+// n3, is above every tet) dies at the triangle.
+extern "C" int dms_d2_pairs_sorted_host(const int64_t *tri_code, const int32_t *tri_max0,
+                                        const int32_t *tri_max1, int64_t ntri, const int32_t *max_rank,
+                                        int64_t n3, int64_t *pair_tri, int32_t *pair_max, int64_t capacity,
+                                        int64_t *npairs)
+{
+    if (!npairs || ntri < 0 || n3 < 0 || capacity < 0) return DMS_E_ARG;
+    if (ntri > 0 && (!tri_code || !tri_max0 || !tri_max1)) return DMS_E_ARG;
+    if (n3 > 0 && !max_rank) return DMS_E_ARG;
+    if (capacity > 0 && (!pair_tri || !pair_max)) return DMS_E_ARG;
+    std::vector<int64_t> rep((size_t)n3 + 1);
+    for (int64_t i = 0; i <= n3; ++i) rep[(size_t)i] = i;
+    auto find = [&](int64_t a) {
+        while (rep[(size_t)a] != a) a = rep[(size_t)a];
+        return a;
+    };
+    auto lower = [&](int64_t a, int64_t b) {  // a below b
+        if (a == n3) return false;
+        if (b == n3) return true;
+        return max_rank[a] < max_rank[b];
+    };
+    int64_t np = 0;
+    for (int64_t s = 0; s < ntri; ++s) {
+        const int64_t t0 = tri_max0[s], t1 = tri_max1[s];
+        if (t0 < 0 || t0 > n3 || t1 < 0 || t1 > n3) return DMS_E_ARG;
+        int64_t r0 = find(t0), r1 = find(t1);
+        if (r0 == r1) continue;
+        if (lower(r1, r0)) std::swap(r0, r1);
+        if (np < capacity) {
+            pair_tri[np] = tri_code[s];
+            pair_max[np] = (int32_t)r0;
+        }
+        ++np;
+        rep[(size_t)r0] = r1;
+        rep[(size_t)t0] = r1;
+    }
+    *npairs = np;
+    return np > capacity ? DMS_E_WORKSPACE : DMS_OK;
+}

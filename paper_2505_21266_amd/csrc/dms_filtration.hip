@@ -119,24 +119,36 @@ __global__ __launch_bounds__(kThreads) void k_cell_place(const int32_t *__restri
     if (i >= count) return;
     const int32_t r = rank[i];
     if (r < 0 || r >= count) return;
-    out_codes[r] = in_codes[i];
+    if (out_codes) out_codes[r] = in_codes[i];
     if (out_key) out_key[r] = in_key[i];
 }
 
-struct SortLayout {
-    size_t hi, lo, hi2, codes2, rank, rws, total;
+// rank[i] = second[first[i]]: the position after the low-word pass, then
+// after the high-word pass.
+__global__ __launch_bounds__(kThreads) void k_compose(const int32_t *__restrict__ first,
+                                                      const int32_t *__restrict__ second, int64_t count,
+                                                      int32_t *__restrict__ rank)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= count) return;
+    const int32_t a = first[i];
+    rank[i] = a >= 0 && a < count ? second[a] : a;
+}
+
+struct RankLayout {
+    size_t hi, lo, hi2, r1, r2, rws, total;
 };
 
-SortLayout sort_layout(int64_t count)
+RankLayout rank_layout(int64_t count)
 {
     const size_t c = (size_t)(count > 0 ? count : 1);
-    SortLayout L{};
+    RankLayout L{};
     size_t off = 0;
     L.hi = off; off += align_up(c * 8, 256);
     L.lo = off; off += align_up(c * 8, 256);
     L.hi2 = off; off += align_up(c * 8, 256);
-    L.codes2 = off; off += align_up(c * 8, 256);
-    L.rank = off; off += align_up(c * 4, 256);
+    L.r1 = off; off += align_up(c * 4, 256);
+    L.r2 = off; off += align_up(c * 4, 256);
     L.rws = off; off += rank_u64_workspace_size(count);
     L.total = off;
     return L;
@@ -145,12 +157,45 @@ SortLayout sort_layout(int64_t count)
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
+size_t cell_rank_workspace_size(int64_t count) { return rank_layout(count).total; }
+
+int launch_cell_ranks(const int64_t *codes, int64_t count, int dim, const int32_t *order, const int64_t *dims,
+                      int32_t *rank, char *ws, uint32_t *flags, hipStream_t s)
+{
+    if (count == 0) return DMS_OK;
+    const RankLayout L = rank_layout(count);
+    uint64_t *hi = (uint64_t *)(ws + L.hi), *lo = (uint64_t *)(ws + L.lo), *hi2 = (uint64_t *)(ws + L.hi2);
+    int32_t *r1 = (int32_t *)(ws + L.r1), *r2 = (int32_t *)(ws + L.r2);
+    const unsigned blocks = blocks_for(count);
+    hipLaunchKernelGGL(k_cell_keys, dim3(blocks), dim3(kThreads), 0, s, codes, count, dim, order, dims[0],
+                       dims[1], dims[2], make_geom(), hi, lo, flags);
+    if (dim < 2) return launch_rank_u64(hi, count, rank, ws + L.rws, flags, s);
+    // the low word first; the high word's stable ranking then orders by
+    // (hi, lo)
+    int st = launch_rank_u64(lo, count, r1, ws + L.rws, flags, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_cell_place, dim3(blocks), dim3(kThreads), 0, s, r1, count, (const int64_t *)nullptr,
+                       hi, (int64_t *)nullptr, hi2);
+    st = launch_rank_u64(hi2, count, r2, ws + L.rws, flags, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_compose, dim3(blocks), dim3(kThreads), 0, s, r1, r2, count, rank);
+    return launch_status();
+}
+
 }  // namespace dms
+
+namespace {
+size_t sort_rank_offset(int64_t count)
+{
+    return dms::align_up((size_t)(count > 0 ? count : 1) * 4, 256);
+}
+}  // namespace
 
 extern "C" size_t dms_critical_sort_workspace_size(int64_t count)
 {
     if (count < 0) return 0;
-    return dms::sort_layout(count).total;
+    return sort_rank_offset(count) + dms::cell_rank_workspace_size(count);
 }
 
 extern "C" int dms_critical_sort(const int64_t *codes, int64_t count, int dim, const int32_t *order,
@@ -164,31 +209,14 @@ extern "C" int dms_critical_sort(const int64_t *codes, int64_t count, int dim, c
     if (count > 2147483647LL) return DMS_E_SIZE;
     if (count == 0) return DMS_OK;
     if (!codes || !order || !sorted || !dev_flags || sorted == codes) return DMS_E_ARG;
-    const SortLayout L = sort_layout(count);
-    if (!workspace || workspace_bytes < L.total) return DMS_E_WORKSPACE;
+    if (!workspace || workspace_bytes < dms_critical_sort_workspace_size(count)) return DMS_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
-    uint64_t *hi = (uint64_t *)(ws + L.hi), *lo = (uint64_t *)(ws + L.lo), *hi2 = (uint64_t *)(ws + L.hi2);
-    int64_t *codes2 = (int64_t *)(ws + L.codes2);
-    int32_t *rank = (int32_t *)(ws + L.rank);
-    const unsigned blocks = blocks_for(count);
-    hipLaunchKernelGGL(k_cell_keys, dim3(blocks), dim3(kThreads), 0, s, codes, count, dim, order, dims[0],
-                       dims[1], dims[2], make_geom(), hi, lo, dev_flags);
-    const int64_t *src = codes;
-    const uint64_t *key = hi;
-    if (dim >= 2) {
-        // the low word first; the high word's stable ranking then orders by
-        // (hi, lo)
-        int st = launch_rank_u64(lo, count, rank, ws + L.rws, dev_flags, s);
-        if (st) return st;
-        hipLaunchKernelGGL(k_cell_place, dim3(blocks), dim3(kThreads), 0, s, rank, count, codes, hi, codes2,
-                           hi2);
-        src = codes2;
-        key = hi2;
-    }
-    int st = launch_rank_u64(key, count, rank, ws + L.rws, dev_flags, s);
+    int32_t *rank = (int32_t *)ws;
+    const int st = launch_cell_ranks(codes, count, dim, order, dims, rank, ws + sort_rank_offset(count),
+                                     dev_flags, s);
     if (st) return st;
-    hipLaunchKernelGGL(k_cell_place, dim3(blocks), dim3(kThreads), 0, s, rank, count, src,
+    hipLaunchKernelGGL(k_cell_place, dim3(blocks_for(count)), dim3(kThreads), 0, s, rank, count, codes,
                        (const uint64_t *)nullptr, sorted, (uint64_t *)nullptr);
     return launch_status();
 }

@@ -44,6 +44,13 @@ size_t order_batch_workspace_size(int64_t n);
 int launch_order_batch(const float *values, int64_t n, const int64_t *foff, int nfields,
                        int32_t *order, char *ws, uint32_t *flags, hipStream_t s);
 
+// Positions of cells of one dimension (codes (maxv << 8) | local index) in
+// the filtration order of Section 2.1: rank[i] = place of codes[i] among
+// them.  A code naming no cell of the grid raises DMS_FLAG_BADCODE.
+size_t cell_rank_workspace_size(int64_t count);
+int launch_cell_ranks(const int64_t *codes, int64_t count, int dim, const int32_t *order, const int64_t *dims,
+                      int32_t *rank, char *ws, uint32_t *flags, hipStream_t s);
+
 // Batched extraction over concatenated whole-field records.
 size_t critical_batch_workspace_size(int64_t n, int nfields);
 int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, int nfields,

@@ -485,6 +485,58 @@ def test_critical_sort_edge_cases():
         dms.critical_sort(corner, 1, og, dims)
 
 
+@pytest.mark.parametrize("shape,kind,seed", [((24, 20, 16), "noise", 91), ((32, 32, 32), "f64", 92),
+                                             ((18, 30, 9), "ties", 93), ((40, 7, 1), "noise", 94),
+                                             ((20, 1, 13), "noise", 95), ((48, 40, 36), "mixture", 96)])
+def test_d2_pairs_gpu_matches_oracle(shape, kind, seed):
+    """GPU dual ascents + host union-find give the oracle's D2 pairs, in the
+    same order; every maximum is paired."""
+    nz, ny, nx = shape
+    v = _field((nx, ny, nz), kind, seed)
+    if kind == "f64":
+        v = inputs.min_gap_pass(v)
+    dims = (nx, ny, nz)
+    o = oracle.order(v)
+    rec, _, _ = oracle.lower_stars(o, dims)
+    crit, _ = oracle.critical_simplices(rec, dims)
+    pt_o, pq_o = oracle.d2_pairs(o, rec, dims, crit[2], crit[3])
+    _say("d2 gpu", shape, kind, len(crit[2]), len(crit[3]))
+    og = dms.order(_dev(v))
+    rg = dms.discrete_gradient(og)
+    lists, counts = dms.critical_simplices(rg, dims)
+    pt, pq = dms.d2_pairs(rg, og, dims, lists[2], lists[3])
+    assert (pt == pt_o).all() and (pq == pq_o).all()
+    assert len(pq) == len(crit[3])
+
+
+def test_d2_backward_config5():
+    """The differentiable D2 form on the 128^3 float64 workload: births and
+    deaths are the highest-vertex values of the oracle's pairs, and the
+    gradient of sum(pers^2) lands on those vertices exactly."""
+    f = inputs.config5()
+    nz, ny, nx = f.shape
+    dims = (nx, ny, nz)
+    o = oracle.order(f)
+    rec, _, _ = oracle.lower_stars(o, dims)
+    crit, _ = oracle.critical_simplices(rec, dims)
+    pt, pq = oracle.d2_pairs(o, rec, dims, crit[2], crit[3])
+    flat = f.reshape(-1)
+    pers = flat[pq >> 8] - flat[pt >> 8]
+    want = np.zeros(flat.size)
+    np.add.at(want, pq >> 8, 2 * pers)
+    np.add.at(want, pt >> 8, -2 * pers)
+    x = _dev(f).requires_grad_(True)
+    births, deaths = dms.PersistenceD2.apply(x)
+    assert (births.detach().cpu().numpy() == flat[pt >> 8]).all()
+    assert (deaths.detach().cpu().numpy() == flat[pq >> 8]).all()
+    ((deaths - births) ** 2).sum().backward()
+    g = x.grad.cpu().numpy().reshape(-1)
+    # sums of at most a few terms per vertex, in another order: relative 1e-10,
+    # with an absolute floor for sums that cancel
+    assert np.all(np.abs(g - want) <= 1e-10 * np.abs(want) + 1e-14 * np.abs(want).max())
+    assert np.abs(want).max() > 0
+
+
 def test_backward_kernel_runs():
     # several deaths on one vertex, given adjacent: summed in pair order
     bc = _dev(np.array([5 << 8, 9 << 8, 11 << 8], np.int64))

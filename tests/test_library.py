@@ -175,3 +175,37 @@ def test_critical_sort_argument_errors(L):
     assert L.dms_critical_sort(fake, 10, 1, fake, bigp, other, fake, ws, fake, None) == 2
     assert L.dms_critical_sort(fake, 100, 1, fake, dp, other, fake, 16, fake, None) == 3
     assert L.dms_critical_sort(None, 0, 1, None, dp, None, None, 0, None, None) == 0  # empty list
+
+
+def test_d2_pairs_sorted_host_hand_case():
+    """The dual union-find on three maxima with ranks 4, 9, 1 and the outside
+    node (index 3), triplets in decreasing triangle order, worked by hand:
+    triangle 300 joins maxima 0 and 1, the lower (0, rank 4) dies; triangle
+    200 joins 2 and the outside, 2 dies; triangle 100 joins 1 and the
+    outside, 1 dies; every maximum is paired."""
+    L = dms.lib()
+    P = ctypes.c_void_p
+    tc = np.array([300, 200, 100], np.int64)
+    t0 = np.array([0, 2, 1], np.int32)
+    t1 = np.array([1, 3, 3], np.int32)
+    mr = np.array([4, 9, 1], np.int32)
+    pt = np.zeros(3, np.int64)
+    pm = np.zeros(3, np.int32)
+    npairs = np.zeros(1, np.int64)
+    st = L.dms_d2_pairs_sorted_host(tc.ctypes.data_as(P), t0.ctypes.data_as(P), t1.ctypes.data_as(P), 3,
+                                    mr.ctypes.data_as(P), 3, pt.ctypes.data_as(P), pm.ctypes.data_as(P), 3,
+                                    npairs.ctypes.data_as(P))
+    assert st == 0 and int(npairs[0]) == 3
+    assert pt.tolist() == [300, 200, 100] and pm.tolist() == [0, 2, 1]
+    bad = np.array([0, 5, 1], np.int32)  # index above n3
+    assert L.dms_d2_pairs_sorted_host(tc.ctypes.data_as(P), bad.ctypes.data_as(P), t1.ctypes.data_as(P), 3,
+                                      mr.ctypes.data_as(P), 3, pt.ctypes.data_as(P), pm.ctypes.data_as(P),
+                                      3, npairs.ctypes.data_as(P)) == 1
+    fake = P(4096)
+    d, dp = _a3([4, 4, 4])
+    assert L.dms_d2_workspace_size(-1, 0) == 0
+    assert L.dms_d2_triplets(None, fake, dp, fake, 1, fake, 1, fake, fake, fake, fake, fake, fake, 1 << 30,
+                             fake, None) == 1
+    assert L.dms_d2_triplets(fake, fake, dp, fake, 10, fake, 1, fake, fake, fake, fake, fake, fake, 16,
+                             fake, None) == 3
+
