@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and differentiable lines")
     ap.add_argument("--cpu-planes", type=int, default=12, help="owned z-planes in the oracle sample")
+    ap.add_argument("--large", action="store_true",
+                    help="time the order-free path (gradient from the values + extraction) on the "
+                         "2048x1920x1536 float32 field instead (one JSON line of its own)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -204,6 +207,72 @@ def bench_differentiable(dev, reps):
             "backward_gpu_ms": round(float(np.median(bwd)), 4), "reps": reps}
 
 
+def bench_large(args, dev):
+    """The paper's largest shape, 2048 x 1920 x 1536 float32 (6.04e9
+    vertices): beyond int32 orders, so the step is the gradient straight
+    from the values plus the extraction."""
+    import torch
+
+    import paper_2505_21266_amd as dms
+    from paper_2505_21266_amd import inputs
+    t0 = time.perf_counter()
+    field = inputs.config_large()
+    gen_s = time.perf_counter() - t0
+    nz, ny, nx = field.shape
+    dims = (nx, ny, nz)
+    n = nx * ny * nz
+    values = torch.from_numpy(field).to(dev)
+    del field
+    rec = torch.empty((n, 4), dtype=torch.int32, device=dev)
+    lo, hi = (0, 0, 0), dims
+    gws = torch.empty(int(dms.lib().dms_gradient_workspace_size(dms._arr3(dims)[1], dms._arr3(lo)[1],
+                                                                    dms._arr3(hi)[1])),
+                      dtype=torch.uint8, device=dev)
+    flags = dms.new_flags(dev)
+    dms.discrete_gradient_values(values, out=rec, workspace=gws, flags=flags, check=False)
+    lists, counts = dms.critical_simplices(rec, dims)
+    cap = counts.cpu().numpy().copy()
+    counts_t = torch.zeros(4, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        dms.discrete_gradient_values(values, out=rec, workspace=gws, flags=flags, check=False)
+        if ev is not None:
+            ev[1].record(stream)
+        dms.critical_simplices(rec, dims, cap=cap, flags=flags, counts=counts_t)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    if int(flags.item()) != 0:
+        raise RuntimeError("device flags set: %d" % int(flags.item()))
+    grad_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    crit_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ms_step = wall / args.steps * 1e3
+    out = {
+        "metric": "discrete-gradient Gvertices/s from the values (gradient + critical) at 2048x1920x1536 f32",
+        "value": round(n / (ms_step / 1e3) / 1e9, 3), "unit": "Gvertices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "mix6g: 2048x1920x1536 float32, 64 Gaussians + 1e-3 U[0,1) noise (seed 6)",
+                   "vertices": n, "critical_counts": [int(c) for c in cap]},
+        "stage_ms": {"gradient_from_values": round(grad_ms, 3), "critical": round(crit_ms, 3)},
+        "input_gen_s": round(gen_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -217,6 +286,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.large:
+        bench_large(args, dev)
+        return
     if args.copy_mib:
         src = torch.ones(args.copy_mib * (1 << 18), dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)

@@ -33,6 +33,19 @@ inline bool grid_size_ok(const int64_t *dims)
     return dims[0] * dims[1] * dims[2] <= lim;
 }
 
+// Grids that need no int32 order (the gradient from the values, the
+// extraction): each side below 2^31, at most 2^40 vertices (record indices in
+// the gradient queue take 40 bits; cell codes (vertex << 8) stay far inside
+// int64).
+inline bool grid_size_values_ok(const int64_t *dims)
+{
+    const int64_t lim = 2147483647LL;
+    if (dims[0] > lim || dims[1] > lim || dims[2] > lim) return false;
+    const int64_t plane = dims[0] * dims[1];
+    if (plane > (1LL << 40)) return false;
+    return dims[2] <= (1LL << 40) / plane;
+}
+
 inline int launch_status()
 {
     hipError_t e = hipGetLastError();

@@ -521,7 +521,7 @@ extern "C" int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3]
 {
     using namespace dms;
     if (!box_valid(dims, lo, hi) || !cap || !counts || !dev_flags) return DMS_E_ARG;
-    if (!grid_size_ok(dims)) return DMS_E_SIZE;
+    if (!grid_size_values_ok(dims)) return DMS_E_SIZE;
     for (int d = 0; d < 4; ++d)
         if (cap[d] < 0) return DMS_E_ARG;
     if ((cap[0] && !crit0) || (cap[1] && !crit1) || (cap[2] && !crit2) || (cap[3] && !crit3))

@@ -441,9 +441,26 @@ __device__ __forceinline__ void gather_orders(const typename Keys::H *tile, int 
 // running a long loop while the block holds its slot, so it ranks them and
 // appends compact entries to a device queue instead; a second kernel pairs
 // the queue in full waves sorted by size.
-//   entry: x, y = ranks of the lower neighbours (lower_ranks), z = record
-//          index, w = size key.
+//   entry: x, y = ranks of the lower neighbours (lower_ranks, 56 bits), the
+//          record index (40 bits: z, and the top byte of y), w = size key.
 constexpr int kQueueChunk = 1024;  // entries per block of the queue kernel
+
+// The ranks take 56 bits (14 nibbles); the record index takes 40 bits, its
+// top 8 in the free byte above the ranks.
+__device__ __forceinline__ uint4 queue_entry(uint64_t rk, int64_t ridx, uint32_t key)
+{
+    const uint64_t r = (uint64_t)ridx;
+    return make_uint4((uint32_t)rk, ((uint32_t)(rk >> 32) & 0x00ffffffu) | ((uint32_t)(r >> 32) << 24),
+                      (uint32_t)r, key);
+}
+__device__ __forceinline__ uint64_t entry_ranks(const uint4 &e)
+{
+    return (uint64_t)e.x | (uint64_t)(e.y & 0x00ffffffu) << 32;
+}
+__device__ __forceinline__ int64_t entry_record(const uint4 &e)
+{
+    return (int64_t)((uint64_t)e.z | (uint64_t)(e.y >> 24) << 32);
+}
 
 struct BlockShared {
     SharedTables T;
@@ -580,9 +597,9 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
         // kernel reads, [0, min(count, qcap)), has been written by this launch
         const uint32_t qb = sh.qbase;
         const uint32_t nq = qb >= qcap ? 0u : min(total, qcap - qb);  // uniform
-        const uint32_t ridx = (uint32_t)(rbase + tx + w0 * ty);
+        const int64_t ridx = rbase + tx + w0 * ty;
         if ((uint32_t)tid < nq)
-            queue[qb + tid] = make_uint4((uint32_t)rk, (uint32_t)(rk >> 32), ridx, size_key(low));
+            queue[qb + tid] = queue_entry(rk, ridx, size_key(low));
         if (nq == total) return;
         // the queue is full: pair the rest here (rare, so unsorted)
         const bool here = (uint32_t)tid >= nq && mine;
@@ -733,7 +750,7 @@ __global__ __launch_bounds__(kThreads) void k_gradient_queue(const uint4 *__rest
         const bool active = i < cnt;
         uint4 e = make_uint4(0xffffffffu, 0x00ffffffu, 0u, 0u);  // no lower neighbour
         if (active) e = queue[start + perm[i]];
-        const uint64_t rk = (uint64_t)e.x | (uint64_t)e.y << 32;
+        const uint64_t rk = entry_ranks(e);
         const int m = __popc(low_of_ranks(rk));
         int mmax = m;
 #pragma unroll
@@ -742,7 +759,7 @@ __global__ __launch_bounds__(kThreads) void k_gradient_queue(const uint4 *__rest
         if (active) {
             uint4 r;
             robins(rk, mmax, T, r);
-            rec[e.z] = r;
+            rec[entry_record(e)] = r;
         }
     }
 }
@@ -989,7 +1006,7 @@ extern "C" size_t dms_gradient_workspace_size(const int64_t dims[3], const int64
                                               const int64_t hi[3])
 {
     using namespace dms;
-    if (!box_valid(dims, lo, hi) || !grid_size_ok(dims)) return 0;
+    if (!box_valid(dims, lo, hi) || !grid_size_values_ok(dims)) return 0;
     return gradient_workspace_size((hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]));
 }
 
@@ -1017,7 +1034,7 @@ extern "C" int dms_discrete_gradient_values(const void *values, int dtype, const
     using namespace dms;
     if (dtype != DMS_F32 && dtype != DMS_F64) return DMS_E_ARG;
     if (!box_valid(dims, lo, hi)) return DMS_E_ARG;
-    if (!grid_size_ok(dims)) return DMS_E_SIZE;
+    if (!grid_size_values_ok(dims)) return DMS_E_SIZE;
     const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
     if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
     if (!values || !rec || !dev_flags) return DMS_E_ARG;

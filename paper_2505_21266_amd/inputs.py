@@ -25,6 +25,9 @@ CONFIG3 = dict(name="gauss1026_ghost", shape=(1026, 1026, 1026), dtype="float32"
                seed=3, owned_lo=(1, 1, 1), owned_hi=(1025, 1025, 1025))
 CONFIG4 = dict(name="batch96", nfields=96, side_lo=32, side_hi=256, seed=4)
 CONFIG5 = dict(name="diff128_f64", shape=(128, 128, 128), dtype="float64", bumps=16, seed=5)
+# the paper's largest dataset shape (2048 x 1920 x 1536, Section 6): beyond
+# int32 orders, so only the gradient from the values and the extraction run
+LARGE = dict(name="mix6g", shape=(1536, 1920, 2048), dtype="float32", bumps=64, seed=6)
 
 
 def _mixture_params(rng, bumps):
@@ -144,6 +147,13 @@ def config5(shape=(128, 128, 128)):
     rng = np.random.default_rng(5)
     f = mixture_field(shape, 16, rng, 1e-4, np.float64)
     return min_gap_pass(f)
+
+
+def config_large(shape=LARGE["shape"]):
+    """2048 x 1920 x 1536 float32 (6.04e9 vertices, 24 GB): 64 Gaussians
+    (seed 6) plus 1e-3 U[0,1), evaluated slab by slab."""
+    rng = np.random.default_rng(LARGE["seed"])
+    return mixture_field(shape, LARGE["bumps"], rng, 1e-3, np.float32, slab=8)
 
 
 def ramp(shape, direction, dtype=np.float64):

@@ -89,7 +89,11 @@ def test_argument_errors(L):
     assert L.dms_discrete_gradient_values(None, 0, dp, lp, hp, fake, None, 0, fake, None) == 1
     assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, None, 0, None, None) == 1
     assert L.dms_discrete_gradient_values(fake, 1, dp, lp, badp, fake, None, 0, fake, None) == 1
-    assert L.dms_discrete_gradient_values(fake, 0, bigp, lp, hp, fake, None, 0, fake, None) == 2
+    # no int32 order on this path: grids past 2^31 vertices are accepted, up to 2^40
+    huge, hugep = _a3([1 << 21, 1 << 20, 4])
+    assert L.dms_discrete_gradient_values(fake, 0, hugep, lp, hp, fake, None, 0, fake, None) == 2
+    assert L.dms_gradient_workspace_size(bigp, lp, hp) > 0
+    assert L.dms_gradient_workspace_size(hugep, lp, hp) == 0
     assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, fake, need - 1, fake, None) == 3
     assert L.dms_discrete_gradient_values(fake, 0, dp, lp, lp, fake, None, 0, fake, None) == 0
     # critical
