@@ -139,12 +139,28 @@ __device__ __forceinline__ int64_t box_vertex(int64_t r, int64_t w0, int64_t w1,
     return i + nx * (j + ny * k);
 }
 
+// Star triangles of each edge (edge_tris), staged in LDS by the fill
+// kernels so that an edge field 3 + j names its head triangle with one read.
+struct EdgeTris {
+    uint8_t t[14][8];
+};
+
+__device__ __forceinline__ void load_edge_tris(EdgeTris &E)
+{
+    const int i = threadIdx.x;
+    if (i < 14 * 8) {
+        const int e = i / 8, j = i % 8;
+        E.t[e][j] = (uint8_t)(j < kTables.edge_ntri[e] ? kTables.edge_tris[e][j] : 0);
+    }
+}
+
 // Writes the critical cells of one record (counts c, first slots at) as
 // codes base | local index.
 __device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint32_t *c,
-                                            const uint64_t *at, int64_t base, int64_t *crit0,
-                                            int64_t *crit1, int64_t *crit2, int64_t *crit3,
-                                            int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
+                                            const uint64_t *at, int64_t base, const EdgeTris &E,
+                                            int64_t *crit0, int64_t *crit1, int64_t *crit2,
+                                            int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2,
+                                            int64_t cap3)
 {
     if (c[0]) {
         if ((int64_t)at[0] < cap0) crit0[at[0]] = base;
@@ -158,9 +174,7 @@ __device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint
     for (int e = 0; e < 14; ++e) {
         const uint32_t f = edge_field(lo, e);
         if (f == 2) crit_e |= 1u << e;
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-            if (j < kTables.edge_ntri[e] && f == 3u + j) head_t |= 1ull << kTables.edge_tris[e][j];
+        if (f >= 3) head_t |= 1ull << E.t[e][(f - 3) & 7];
     }
 #pragma unroll
     for (int t = 0; t < 36; ++t) {
@@ -302,7 +316,7 @@ __device__ __forceinline__ void fill_slots(const uint64_t *pk, const uint64_t *_
 // All records of one tile (the whole block).
 __device__ __forceinline__ void fill_tile_full(
     const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
-    int64_t w0, int64_t w1, int64_t lo0, int64_t lo1, int64_t lo2, int64_t nx, int64_t ny,
+    int64_t w0, int64_t w1, int64_t lo0, int64_t lo1, int64_t lo2, int64_t nx, int64_t ny, const EdgeTris &E,
     int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
     int64_t cap2, int64_t cap3)
 {
@@ -317,7 +331,7 @@ __device__ __forceinline__ void fill_tile_full(
 #pragma unroll
         for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
         const int64_t v = box_vertex(r0 + k, w0, w1, lo0, lo1, lo2, nx, ny);
-        write_codes(lo[k], hi[k], c, at[k], v << 8, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+        write_codes(lo[k], hi[k], c, at[k], v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
     }
 }
 
@@ -330,10 +344,13 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill(
     int64_t lo0, int64_t lo1, int64_t lo2, int64_t nx, int64_t ny, int64_t *crit0, int64_t *crit1,
     int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
 {
+    __shared__ EdgeTris E;
     const uint32_t n = ncand[blockIdx.x];
     if (n == 0) return;  // uniform
+    load_edge_tris(E);
+    __syncthreads();
     if (n > (uint32_t)kCand) {
-        fill_tile_full(rec, nbox, offs, ntiles, w0, w1, lo0, lo1, lo2, nx, ny, crit0, crit1, crit2,
+        fill_tile_full(rec, nbox, offs, ntiles, w0, w1, lo0, lo1, lo2, nx, ny, E, crit0, crit1, crit2,
                        crit3, cap0, cap1, cap2, cap3);
         return;
     }
@@ -370,7 +387,7 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill(
         c[d] = lane16(pk, d);
     }
     const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
-    write_codes(lo, hi, c, at, v << 8, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+    write_codes(lo, hi, c, at, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 }
 
 __global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *counts, int64_t cap0,
@@ -397,11 +414,13 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
     int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
 {
     __shared__ int64_t so[kMaxBatchFields + 1];
+    __shared__ EdgeTris E;
     for (int i = threadIdx.x; i <= nfields; i += kThreads) so[i] = foff[i];
+    load_edge_tris(E);
     const int64_t r0 = (int64_t)blockIdx.x * kTileRecs + (int64_t)threadIdx.x * kPerThread;
     uint64_t lo[kPerThread], hi[kPerThread], pk[kPerThread], at[kPerThread][4];
     load_recs(rec, nbox, r0, lo, hi, pk);
-    fill_slots(pk, offs, ntiles, at);  // its barriers also publish so[]
+    fill_slots(pk, offs, ntiles, at);  // its barriers also publish so[] and E
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         const int64_t r = r0 + k;
@@ -417,7 +436,7 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
         uint32_t c[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
-        write_codes(lo[k], hi[k], c, at[k], (r - so[f0]) << 8, crit0, crit1, crit2, crit3, cap0, cap1,
+        write_codes(lo[k], hi[k], c, at[k], (r - so[f0]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1,
                     cap2, cap3);
     }
 }

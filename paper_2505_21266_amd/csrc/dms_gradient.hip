@@ -250,18 +250,23 @@ __device__ __forceinline__ void robins(uint64_t rank_of, int mmax, const SharedT
         cnt.dec(T.cont[d] & kTriBits);
     }
     for (int step = 0; step < 80; ++step) {
+        // the cells with one unpaired facet if there are any, else the
+        // unpaired cells without one; one bit-sliced minimum serves both
+        // cases, so lanes of a wave that are in different cases share it
         const uint64_t one = ftq & cnt.b0 & ~cnt.b1;
+        uint64_t S = one ? one : (ftq & ~cnt.b0 & ~cnt.b1);
+        if (S == 0 && fr == 0) break;
+#pragma unroll
+        for (int b = 13; b >= 0; --b) {
+            if (b < mmax) {
+                const uint64_t z = S & nkp[b];
+                S = z ? z : S;
+            }
+        }
+        const bool have_a = S != 0;
+        const int a = have_a ? __ffsll((unsigned long long)S) - 1 : 0;
         if (one) {
             // pair the smallest cell with one unpaired facet with that facet
-            uint64_t S = one;
-#pragma unroll
-            for (int b = 13; b >= 0; --b) {
-                if (b < mmax) {
-                    const uint64_t z = S & nkp[b];
-                    S = z ? z : S;
-                }
-            }
-            const int a = __ffsll((unsigned long long)S) - 1;
             const uint64_t fa = T.facet[a];
             uint64_t D;
             if (a < 36) {  // triangle a takes its only unpaired edge e
@@ -286,17 +291,6 @@ __device__ __forceinline__ void robins(uint64_t rank_of, int mmax, const SharedT
         }
         // no cell has exactly one unpaired facet: the smallest unpaired edge or
         // cell without unpaired facets is critical
-        uint64_t S = ftq & ~cnt.b0 & ~cnt.b1;
-        if (S == 0 && fr == 0) break;
-#pragma unroll
-        for (int b = 13; b >= 0; --b) {
-            if (b < mmax) {
-                const uint64_t z = S & nkp[b];
-                S = z ? z : S;
-            }
-        }
-        const bool have_a = S != 0;
-        const int a = have_a ? __ffsll((unsigned long long)S) - 1 : 0;
         bool edge_wins = fr != 0 && !have_a;
         const int re = fr ? __ffs(fr) - 1 : 31;
         if (fr != 0 && have_a) {
