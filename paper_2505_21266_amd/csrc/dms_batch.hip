@@ -5,8 +5,8 @@
 // All fields are concatenated.  The order is one radix sort on a composite
 // key (field index above the float32 value key), so each field's ranks are
 // its global positions minus the field's offset.  The gradient is one
-// persistent launch over the (field, tile) list; the extraction one pass over
-// all records.  The first run records these launches into a hipGraph on a
+// launch over the (field, tile) list, a block per tile; the extraction one
+// pass over all records.  The first run records these launches into a hipGraph on a
 // private capture stream; later runs with the same arguments replay it on the
 // caller's stream.  An autotuner picks the gradient tile shape per batch
 // (timed on the first run, remembered in an optional cache file).
@@ -33,6 +33,7 @@ struct dms_batch {
     dms::BatchField *d_fields = nullptr;
     int64_t *d_off = nullptr;
     int64_t *d_tiles[dms::kGradVariants] = {nullptr, nullptr, nullptr};
+    uint16_t *d_tile_field[dms::kGradVariants] = {nullptr, nullptr, nullptr};  // field of each tile
     int64_t tiles[dms::kGradVariants] = {0, 0, 0};
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -106,8 +107,8 @@ int enqueue_all(dms_batch *b, const void *values, int32_t *order, uint32_t *rec,
                                      w.order, flags, s);
     if (st) return st;
     st = dms::launch_gradient_batch(b->variant, order, b->d_fields, b->nfields, b->d_tiles[b->variant],
-                                    b->tiles[b->variant], b->total, rec,
-                                    dms::gradient_batch_grid(b->variant), w.grad, s);
+                                    b->d_tile_field[b->variant], b->tiles[b->variant], b->total, rec,
+                                    w.grad, s);
     if (st) return st;
     return dms::launch_critical_batch(rec, b->total, b->d_off, b->nfields, b->d_fields, crit, cap,
                                       counts, offsets, w.crit, flags, s);
@@ -124,8 +125,9 @@ int autotune(dms_batch *b, const int32_t *order, uint32_t *rec, char *gws, hipSt
         float t = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
-            int st = dms::launch_gradient_batch(v, order, b->d_fields, b->nfields, b->d_tiles[v], b->tiles[v],
-                                                b->total, rec, dms::gradient_batch_grid(v), gws, s);
+            int st = dms::launch_gradient_batch(v, order, b->d_fields, b->nfields, b->d_tiles[v],
+                                                b->d_tile_field[v], b->tiles[v],
+                                                b->total, rec, gws, s);
             (void)hipEventRecord(e1, s);
             if (st) return st;
             if (hipEventSynchronize(e1) != hipSuccess) return DMS_E_HIP;
@@ -188,8 +190,13 @@ extern "C" int dms_batch_create(const int64_t *dims, int nfields, int dtype, int
             ts[f + 1] = ts[f] + ((d[0] + gx - 1) / gx) * ((d[1] + gy - 1) / gy) * d[2];
         }
         b->tiles[v] = ts[nfields];
+        std::vector<uint16_t> tf((size_t)(ts[nfields] > 0 ? ts[nfields] : 1));
+        for (int f = 0; f < nfields; ++f)
+            for (int64_t t = ts[f]; t < ts[f + 1]; ++t) tf[(size_t)t] = (uint16_t)f;
         ok = hipMalloc(&b->d_tiles[v], sizeof(int64_t) * (nfields + 1)) == hipSuccess &&
-             hipMemcpy(b->d_tiles[v], ts.data(), sizeof(int64_t) * (nfields + 1), hipMemcpyHostToDevice) == hipSuccess;
+             hipMemcpy(b->d_tiles[v], ts.data(), sizeof(int64_t) * (nfields + 1), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMalloc(&b->d_tile_field[v], sizeof(uint16_t) * tf.size()) == hipSuccess &&
+             hipMemcpy(b->d_tile_field[v], tf.data(), sizeof(uint16_t) * tf.size(), hipMemcpyHostToDevice) == hipSuccess;
     }
     ok = ok && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess &&
          dms::ensure_regular_table(b->cap_stream) == DMS_OK;
@@ -273,6 +280,9 @@ extern "C" void dms_batch_destroy(dms_batch *b)
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     (void)hipFree(b->d_fields);
     (void)hipFree(b->d_off);
-    for (int v = 0; v < dms::kGradVariants; ++v) (void)hipFree(b->d_tiles[v]);
+    for (int v = 0; v < dms::kGradVariants; ++v) {
+        (void)hipFree(b->d_tiles[v]);
+        (void)hipFree(b->d_tile_field[v]);
+    }
     delete b;
 }

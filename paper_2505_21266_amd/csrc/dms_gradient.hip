@@ -676,12 +676,17 @@ __global__ __launch_bounds__(kThreads, 8) void k_gradient(const void *__restrict
                                 queue, qcount, qcap, flags, sh, tile);
 }
 
-// Batched form: many whole fields, concatenated; a persistent grid walks the
+// Batched form: many whole fields, concatenated; one block per tile of the
 // (field, tile) list, field f owning tiles [tile_start[f], tile_start[f+1]).
+// tile_field[t] names the field of tile t, so a block finds its field with
+// one read, and the kernel keeps the single-field kernel's registers and LDS
+// (a persistent grid walking the tiles held the walk's 64-bit state in
+// scalar registers and spilled).
 template <int GX, int GY>
-__global__ __launch_bounds__(kThreads, 5) void k_gradient_batch(const int32_t *__restrict__ order,
+__global__ __launch_bounds__(kThreads, 8) void k_gradient_batch(const int32_t *__restrict__ order,
                                                                 const BatchField *__restrict__ fields,
-                                                                int nfields, const int64_t *tile_start,
+                                                                const int64_t *__restrict__ tile_start,
+                                                                const uint16_t *__restrict__ tile_field,
                                                                 uint4 *__restrict__ rec,
                                                                 const uint4 *__restrict__ defect8,
                                                                 uint4 *__restrict__ queue,
@@ -689,27 +694,15 @@ __global__ __launch_bounds__(kThreads, 5) void k_gradient_batch(const int32_t *_
 {
     __shared__ BlockShared sh;
     __shared__ int32_t tile[Tile<GX, GY>::kHalo];
-    __shared__ int64_t tstart[kMaxBatchFields + 1];
     load_tables(sh.T);
-    for (int i = threadIdx.x; i <= nfields; i += kThreads) tstart[i] = tile_start[i];
-    __syncthreads();
-    const int64_t total = tstart[nfields];
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int lo = 0, hi = nfields - 1;  // last field with tstart <= t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tstart[mid] <= t) lo = mid; else hi = mid - 1;
-        }
-        lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: the block's field
-        const BatchField F = fields[lo];
-        const int64_t bxc = (F.n[0] + GX - 1) / GX, byc = (F.n[1] + GY - 1) / GY;
-        const int64_t k = t - tstart[lo];
-        const int64_t bx = k % bxc, by = (k / bxc) % byc, bz = k / (bxc * byc);
-        gradient_tile<RankKeys, GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1],
-                                        F.n[2], bx, by, bz, F.off, rec, defect8, queue, qcount, qcap,
-                                        nullptr, sh, tile);
-        __syncthreads();  // the next tile reuses the shared buffers
-    }
+    const int64_t t = blockIdx.x;
+    const int f = tile_field[t];
+    const BatchField F = fields[f];
+    const int64_t bxc = (F.n[0] + GX - 1) / GX, byc = (F.n[1] + GY - 1) / GY;
+    const int64_t k = t - tile_start[f];
+    const int64_t bx = k % bxc, by = (k / bxc) % byc, bz = k / (bxc * byc);
+    gradient_tile<RankKeys, GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1], F.n[2], bx,
+                                    by, bz, F.off, rec, defect8, queue, qcount, qcap, nullptr, sh, tile);
 }
 
 __global__ void k_queue_reset(uint32_t *qcount) { *qcount = 0; }
@@ -887,20 +880,6 @@ static const uint4 *defect8_table()
     return (g_regular_ready.load() >> dev) & 1u ? g_defect8_ptr[dev] : nullptr;
 }
 
-int gradient_batch_grid(int variant)
-{
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e;
-    switch (variant) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<64, 16>, kThreads, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<32, 32>, kThreads, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_gradient_batch<16, 64>, kThreads, 0); break;
-    }
-    if (e != hipSuccess || per < 1) per = 1;
-    return cus * per;
-}
 
 // Queue of general vertices: a counter, then qcap 16-byte entries; room for
 // one vertex in 16 plus a chunk.
@@ -972,18 +951,19 @@ int launch_gradient(int variant, const int32_t *order, const int64_t *dims, cons
 }
 
 int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
-                          const int64_t *tile_start, int64_t total_tiles, int64_t total_verts,
-                          uint32_t *rec, int grid, char *ws, hipStream_t s)
+                          const int64_t *tile_start, const uint16_t *tile_field, int64_t total_tiles,
+                          int64_t total_verts, uint32_t *rec, char *ws, hipStream_t s)
 {
+    (void)nfields;
     if (total_tiles == 0) return DMS_OK;
-    const unsigned g = (unsigned)(total_tiles < grid ? total_tiles : grid);
+    if (total_tiles > 2147483647LL) return DMS_E_SIZE;
     const uint4 *d8 = defect8_table();
     uint4 *queue;
     uint32_t *qcount, qcap;
     queue_begin(ws, total_verts, s, &queue, &qcount, &qcap);
-#define DMS_LAUNCH(GXV)                                                                          \
-    hipLaunchKernelGGL((k_gradient_batch<GXV, kTileVerts / GXV>), dim3(g), dim3(kThreads), 0, s,  \
-                       order, fields, nfields, tile_start, (uint4 *)rec, d8, queue, qcount, qcap)
+#define DMS_LAUNCH(GXV)                                                                               \
+    hipLaunchKernelGGL((k_gradient_batch<GXV, kTileVerts / GXV>), dim3((unsigned)total_tiles), dim3(kThreads), \
+                       0, s, order, fields, tile_start, tile_field, (uint4 *)rec, d8, queue, qcount, qcap)
     switch (variant) {
     case 0: DMS_LAUNCH(64); break;
     case 1: DMS_LAUNCH(32); break;

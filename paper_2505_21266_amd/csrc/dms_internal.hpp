@@ -27,10 +27,9 @@ int ensure_regular_table(hipStream_t s);
 size_t gradient_workspace_size(int64_t owned);
 int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
                     const int64_t *hi, uint32_t *rec, char *ws, hipStream_t s);
-int gradient_batch_grid(int variant);  // persistent grid size (CUs x resident blocks)
 int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
-                          const int64_t *tile_start, int64_t total_tiles, int64_t total_verts,
-                          uint32_t *rec, int grid, char *ws, hipStream_t s);
+                          const int64_t *tile_start, const uint16_t *tile_field, int64_t total_tiles,
+                          int64_t total_verts, uint32_t *rec, char *ws, hipStream_t s);
 
 // Ranks of n 64-bit unsigned keys (rank[i] = position of key i in the
 // ascending stable sort), with the order passes.

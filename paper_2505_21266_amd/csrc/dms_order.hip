@@ -35,15 +35,20 @@ constexpr int kRadix = 256;
 // (field index in bits 32..39 above the float32 key).
 constexpr int kBatchPasses = 5;
 
-// field of element i: the last f with foff[f] <= i (binary search)
-__device__ __forceinline__ int field_of(const int64_t *foff, int nfields, int64_t i)
+// field of element i: the last f in [lo, hi] with foff[f] <= i (binary
+// search; the caller knows i lies in one of fields lo..hi)
+__device__ __forceinline__ int field_between(const int64_t *foff, int lo, int hi, int64_t i)
 {
-    int lo = 0, hi = nfields - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (foff[mid] <= i) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+__device__ __forceinline__ int field_of(const int64_t *foff, int nfields, int64_t i)
+{
+    return field_between(foff, 0, nfields - 1, i);
 }
 
 // Tile processed by this block.  Blocks are dealt round-robin to the 8 XCDs
@@ -250,6 +255,15 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
     K key[kItems];
     uint32_t id[kItems];
     uint32_t rank[kItems];
+    // a batch tile usually lies in one field: the fields of its first and
+    // last elements bound the search for the others
+    int f_first = 0, f_last = 0;
+    if constexpr (kFirst && sizeof(K) == 8) {
+        if (foff && count > 0) {
+            f_first = field_of(foff, nfields, t0);
+            f_last = field_of(foff, nfields, t0 + count - 1);
+        }
+    }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int li = local_index(wave, k, lane);
@@ -259,7 +273,10 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
             bool nan;
             key[k] = load_key<V, K, kFirst>(src, t0 + li, nan);
             if constexpr (kFirst && sizeof(K) == 8) {
-                if (foff) key[k] |= (K)field_of(foff, nfields, t0 + li) << 32;
+                if (foff) {
+                    const int f = f_first == f_last ? f_first : field_between(foff, f_first, f_last, t0 + li);
+                    key[k] |= (K)f << 32;
+                }
             }
             id[k] = kFirst ? (uint32_t)(t0 + li) : src_ids[t0 + li];
         }
