@@ -405,40 +405,112 @@ __global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *cou
 }
 
 
+// Field of record r of a batch (so: the fields' first records, in LDS).
+__device__ __forceinline__ int record_field(const int64_t *so, int nfields, int64_t r)
+{
+    int lo = 0, hi = nfields - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (so[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Batched fill: records of whole fields concatenated; codes carry the
-// field-local vertex id; the first record of each field publishes the
-// field's first slot in every list.
+// field-local vertex id.  As k_crit_fill: a tile with no listed records is
+// skipped, one with at most kCand is served by one wave, a fuller one is
+// re-read whole.
 __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
     const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
-    const int64_t *__restrict__ foff, int nfields, int64_t *fstart, int64_t *crit0, int64_t *crit1,
-    int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
+    const uint16_t *__restrict__ cand, const uint32_t *__restrict__ ncand, const int64_t *__restrict__ foff,
+    int nfields, int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
+    int64_t cap2, int64_t cap3)
 {
     __shared__ int64_t so[kMaxBatchFields + 1];
     __shared__ EdgeTris E;
+    const uint32_t n = ncand[blockIdx.x];
+    if (n == 0) return;  // uniform
     for (int i = threadIdx.x; i <= nfields; i += kThreads) so[i] = foff[i];
     load_edge_tris(E);
-    const int64_t r0 = (int64_t)blockIdx.x * kTileRecs + (int64_t)threadIdx.x * kPerThread;
-    uint64_t lo[kPerThread], hi[kPerThread], pk[kPerThread], at[kPerThread][4];
-    load_recs(rec, nbox, r0, lo, hi, pk);
-    fill_slots(pk, offs, ntiles, at);  // its barriers also publish so[] and E
+    __syncthreads();
+    if (n > (uint32_t)kCand) {
+        const int64_t r0 = (int64_t)blockIdx.x * kTileRecs + (int64_t)threadIdx.x * kPerThread;
+        uint64_t lo[kPerThread], hi[kPerThread], pk[kPerThread], at[kPerThread][4];
+        load_recs(rec, nbox, r0, lo, hi, pk);
+        fill_slots(pk, offs, ntiles, at);
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-        const int64_t r = r0 + k;
-        if (r >= nbox) continue;
-        int f0 = 0, f1 = nfields - 1;
-        while (f0 < f1) {
-            const int mid = (f0 + f1 + 1) >> 1;
-            if (so[mid] <= r) f0 = mid; else f1 = mid - 1;
+        for (int k = 0; k < kPerThread; ++k) {
+            const int64_t r = r0 + k;
+            if (r >= nbox || pk[k] == 0) continue;
+            const int f = record_field(so, nfields, r);
+            uint32_t c[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
+            write_codes(lo[k], hi[k], c, at[k], (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1,
+                        cap2, cap3);
         }
-        if (r == so[f0])
-            for (int d = 0; d < 4; ++d) fstart[(int64_t)d * (nfields + 1) + f0] = (int64_t)at[k][d];
-        if (pk[k] == 0) continue;
-        uint32_t c[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
-        write_codes(lo[k], hi[k], c, at[k], (r - so[f0]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1,
-                    cap2, cap3);
+        return;
     }
+    if (threadIdx.x >= kWave) return;
+    const int lane = threadIdx.x;
+    const bool active = (uint32_t)lane < n;
+    uint64_t lo = 0, hi = 0, pk = 0;
+    int64_t r = 0;
+    if (active) {
+        r = (int64_t)blockIdx.x * kTileRecs + cand[(int64_t)blockIdx.x * kCand + lane];
+        if (r < nbox) {
+            const uint4 w = rec[r];
+            lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
+            hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
+            uint32_t c[4];
+            count_critical(lo, hi, c);
+            pk = pack4(c);
+        }
+    }
+    uint64_t inc = pk;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    const uint64_t ex = inc - pk;
+    if (pk == 0) return;
+    uint64_t at[4];
+    uint32_t c[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        at[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles] + lane16(ex, d);
+        c[d] = lane16(pk, d);
+    }
+    const int f = record_field(so, nfields, r);
+    write_codes(lo, hi, c, at, (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+}
+
+// First slot of every field in every list: the scanned count of its first
+// record's tile plus the counts of the tile's records before it (one block
+// per field).
+__global__ __launch_bounds__(kThreads) void k_crit_fstart_batch(const uint4 *__restrict__ rec,
+                                                                const uint64_t *__restrict__ offs,
+                                                                int64_t ntiles,
+                                                                const int64_t *__restrict__ foff,
+                                                                int nfields, int64_t *fstart)
+{
+    const int f = blockIdx.x;
+    const int64_t r = foff[f];
+    const int64_t tile = r / kTileRecs;
+    uint64_t sum = 0;
+    for (int64_t q = tile * kTileRecs + threadIdx.x; q < r; q += kThreads) {
+        const uint4 w = rec[q];
+        uint32_t c[4];
+        count_critical((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), c);
+        sum += pack4(c);
+    }
+    uint64_t total;
+    block_exclusive_scan<uint64_t>(sum, &total);
+    if (threadIdx.x == 0 && tile < ntiles)
+        for (int d = 0; d < 4; ++d)
+            fstart[(int64_t)d * (nfields + 1) + f] =
+                (int64_t)(offs[(int64_t)d * ntiles + tile] - offs[(int64_t)d * ntiles] + lane16(total, d));
 }
 
 __global__ void k_crit_finish_batch(const uint64_t *offs, int64_t ntiles, int nfields, int64_t *fstart,
@@ -472,38 +544,6 @@ __global__ void k_crit_empty(int64_t *counts)
 
 namespace dms {
 
-size_t critical_batch_workspace_size(int64_t n, int nfields)
-{
-    (void)nfields;
-    const int64_t ntiles = (n + kTileRecs - 1) / kTileRecs;
-    const int64_t len = 4 * ntiles + 1;
-    return align_up((size_t)len * 8, 256) + scan_partials_bytes(len, 8);
-}
-
-int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, int nfields,
-                          const BatchField *fields, int64_t *const crit[4], const int64_t cap[4],
-                          int64_t *counts, int64_t *offsets, char *ws, uint32_t *flags,
-                          hipStream_t s)
-{
-    (void)fields;
-    const int64_t ntiles = (n + kTileRecs - 1) / kTileRecs;
-    const int64_t len = 4 * ntiles + 1;
-    uint64_t *tc = (uint64_t *)ws;
-    uint64_t *partials = (uint64_t *)(ws + align_up((size_t)len * 8, 256));
-    hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       n, tc, ntiles, nullptr, nullptr);
-    exclusive_scan<uint64_t>(tc, len, partials, s);
-    hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
-                       (const uint4 *)rec, n, tc, ntiles, foff, nfields, offsets, crit[0], crit[1],
-                       crit[2], crit[3], cap[0], cap[1], cap[2], cap[3]);
-    hipLaunchKernelGGL(k_crit_finish_batch, dim3(1), dim3(256), 0, s, tc, ntiles, nfields, offsets,
-                       counts, cap[0], cap[1], cap[2], cap[3], flags);
-    return launch_status();
-}
-
-}  // namespace dms
-
-namespace {
 // Single-field workspace: tile counts (4 x ntiles + 1, scanned in place),
 // scan partials, candidate positions (kCand per tile), candidate counts.
 struct CritLayout {
@@ -514,14 +554,49 @@ CritLayout crit_layout(int64_t ntiles)
 {
     const int64_t len = 4 * ntiles + 1;
     CritLayout L{};
-    size_t off = dms::align_up((size_t)len * 8, 256);
-    L.partials = off; off += dms::scan_partials_bytes(len, 8);
-    L.cand = off; off += dms::align_up((size_t)ntiles * dms::kCand * 2, 256);
-    L.ncand = off; off += dms::align_up((size_t)ntiles * 4, 256);
+    size_t off = align_up((size_t)len * 8, 256);
+    L.partials = off; off += scan_partials_bytes(len, 8);
+    L.cand = off; off += align_up((size_t)ntiles * kCand * 2, 256);
+    L.ncand = off; off += align_up((size_t)ntiles * 4, 256);
     L.total = off;
     return L;
 }
-}  // namespace
+
+size_t critical_batch_workspace_size(int64_t n, int nfields)
+{
+    (void)nfields;
+    return crit_layout((n + kTileRecs - 1) / kTileRecs).total;
+}
+
+int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, int nfields,
+                          const BatchField *fields, int64_t *const crit[4], const int64_t cap[4],
+                          int64_t *counts, int64_t *offsets, char *ws, uint32_t *flags,
+                          hipStream_t s)
+{
+    (void)fields;
+    const int64_t ntiles = (n + kTileRecs - 1) / kTileRecs;
+    const int64_t len = 4 * ntiles + 1;
+    const CritLayout L = crit_layout(ntiles);
+    uint64_t *tc = (uint64_t *)ws;
+    uint64_t *partials = (uint64_t *)(ws + L.partials);
+    uint16_t *cand = (uint16_t *)(ws + L.cand);
+    uint32_t *ncand = (uint32_t *)(ws + L.ncand);
+    hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
+                       n, tc, ntiles, cand, ncand);
+    exclusive_scan<uint64_t>(tc, len, partials, s);
+    hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
+                       (const uint4 *)rec, n, tc, ntiles, cand, ncand, foff, nfields, crit[0], crit[1],
+                       crit[2], crit[3], cap[0], cap[1], cap[2], cap[3]);
+    hipLaunchKernelGGL(k_crit_fstart_batch, dim3((unsigned)nfields), dim3(kThreads), 0, s, (const uint4 *)rec,
+                       tc, ntiles, foff, nfields, offsets);
+    hipLaunchKernelGGL(k_crit_finish_batch, dim3(1), dim3(256), 0, s, tc, ntiles, nfields, offsets,
+                       counts, cap[0], cap[1], cap[2], cap[3], flags);
+    return launch_status();
+}
+
+}  // namespace dms
+
+
 
 extern "C" size_t dms_critical_workspace_size(const int64_t dims[3], const int64_t lo[3],
                                               const int64_t hi[3])
