@@ -379,11 +379,34 @@ def d0_pairs_host(rec_np, order_np, dims, crit1_np):
     return pe[:k], pm[:k]
 
 
+def _require_whole_grid(rec, order_t, dims, lists):
+    """Arguments of the pairings: whole-grid records and order on the GPU,
+    int64 critical lists on the GPU."""
+    import torch
+    _require_gpu(rec, "rec")
+    _require_gpu(order_t, "order")
+    n = int(dims[0]) * int(dims[1]) * int(dims[2])
+    if rec.dtype != torch.int32 or rec.numel() != 4 * n:
+        raise ValueError("rec must hold the int32 records of the whole grid (%d x 4)" % n)
+    if order_t.dtype != torch.int32 or order_t.numel() != n:
+        raise ValueError("order must be the int32 order of the whole grid (%d)" % n)
+    for nm, t in lists:
+        _require_gpu(t, nm)
+        if t.dtype != torch.int64:
+            raise TypeError("%s must be int64 codes" % nm)
+
+
 def critical_sort(codes, dim, order_t, dims, out=None, flags=None, check=True):
     """Critical cells of dimension dim (int64 device codes, as
     critical_simplices lists them) in the filtration order of Section 2.1
     (dms_critical_sort).  Returns a new int64 tensor unless out is given."""
     import torch
+    _require_gpu(codes, "codes")
+    _require_gpu(order_t, "order")
+    if codes.dtype != torch.int64 or order_t.dtype != torch.int32:
+        raise TypeError("codes must be int64 and order int32")
+    if not 0 <= int(dim) <= 3:
+        raise ValueError("dim must be 0..3")
     L = lib()
     n = int(codes.numel())
     if out is None:
@@ -409,6 +432,7 @@ def d0_pairs(rec, order_t, dims, crit0, crit1):
     (dms_d0_pairs_sorted_host).  rec/order_t/crit0/crit1 are device tensors
     of the whole grid.  Returns numpy (pair_edge codes, pair_min vertices)."""
     import torch
+    _require_whole_grid(rec, order_t, dims, [("crit0", crit0), ("crit1", crit1)])
     L = lib()
     P = ctypes.c_void_p
     dev = rec.device
@@ -451,6 +475,7 @@ def d2_pairs(rec, order_t, dims, crit2, crit3):
     crit3 are device tensors of the whole grid.  Returns numpy (pair_tri
     codes, pair_tet codes)."""
     import torch
+    _require_whole_grid(rec, order_t, dims, [("crit2", crit2), ("crit3", crit3)])
     L = lib()
     P = ctypes.c_void_p
     dev = rec.device

@@ -213,3 +213,18 @@ def test_d2_pairs_sorted_host_hand_case():
     assert L.dms_d2_triplets(fake, fake, dp, fake, 10, fake, 1, fake, fake, fake, fake, fake, fake, 16,
                              fake, None) == 3
 
+
+
+def test_bindings_reject_host_tensors():
+    """The pairings and the filtration sort have no CPU path: host tensors
+    and wrong shapes are refused before any launch."""
+    torch = pytest.importorskip("torch")
+    c = torch.zeros(4, dtype=torch.int64)
+    o = torch.zeros(8, dtype=torch.int32)
+    r = torch.zeros((8, 4), dtype=torch.int32)
+    with pytest.raises(TypeError):
+        dms.critical_sort(c, 1, o, (2, 2, 2))
+    with pytest.raises(TypeError):
+        dms.d0_pairs(r, o, (2, 2, 2), c, c)
+    with pytest.raises(TypeError):
+        dms.d2_pairs(r, o, (2, 2, 2), c, c)
