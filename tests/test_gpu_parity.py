@@ -192,6 +192,54 @@ def test_gradient_full_block_sampled():
     del rec, o
 
 
+def test_config1_exact():
+    """The 64^3 white-noise workload end to end: order, every record and the
+    four critical lists equal the oracle's."""
+    v = inputs.config1()
+    dims = (64, 64, 64)
+    o = oracle.order(v)
+    rec, _, _ = oracle.lower_stars(o, dims)
+    crit, _ = oracle.critical_simplices(rec, dims)
+    _say("config1 exact")
+    og = dms.order(_dev(v))
+    assert (og.cpu().numpy() == o).all()
+    rg = dms.discrete_gradient(og)
+    assert (rg.cpu().numpy().view(np.uint32) == rec).all()
+    lists, counts = dms.critical_simplices(rg, dims)
+    for d in range(4):
+        assert (lists[d].cpu().numpy() == np.asarray(crit[d], np.int64)).all(), d
+
+
+def test_config2_sampled():
+    """The 512^3 64-Gaussian workload: the order is the unique (value, id)
+    sort, 60000 sampled records equal the oracle's (from the values), the
+    critical lists restricted to the sample are exactly the critical cells of
+    those records, and the Euler characteristic is 1."""
+    v = inputs.config2()
+    nz, ny, nx = v.shape
+    dims = (nx, ny, nz)
+    n = nx * ny * nz
+    vids = np.random.default_rng(22).integers(0, n, 60000)
+    want = oracle.lower_stars_sampled(v, dims, vids)
+    _say("config2 sampled")
+    vt = _dev(v)
+    og = dms.order(vt)
+    _check_order_gpu(vt, og)
+    rg = dms.discrete_gradient(og)
+    assert (rg[_dev(vids)].cpu().numpy().view(np.uint32) == want).all()
+    lists, counts = dms.critical_simplices(rg, dims)
+    c = counts.cpu().numpy()
+    assert c[0] - c[1] + c[2] - c[3] == 1
+    expect = [set() for _ in range(4)]
+    for r4, x in zip(want, vids):
+        for d, code in _critical_codes_of(r4, int(x)):
+            expect[d].add(code)
+    for d in range(4):
+        codes = lists[d].cpu().numpy()
+        assert set(int(x) for x in codes[np.isin(codes >> 8, vids)]) == expect[d], d
+    assert sum(len(e) for e in expect) > 10
+
+
 # -------------------------------------------------------------- gradient
 
 GRAD_CASES = [
