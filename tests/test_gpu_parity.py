@@ -557,6 +557,41 @@ def test_d2_pairs_gpu_matches_oracle(shape, kind, seed):
     assert len(pq) == len(crit[3])
 
 
+def test_d0_finite_differences_config5():
+    """The differentiable form on the 128^3 float64 workload, checked by
+    central finite differences of its own GPU forward on a 16^3 sub-grid:
+    every vertex of the sub-grid whose analytic gradient is non-zero, and 48
+    whose gradient is zero.  The step is a quarter of the smallest value gap,
+    so the pairing, and with it the loss's quadratic form, does not change."""
+    from paper_2505_21266_amd.autograd import d0_loss
+    f = inputs.config5()
+    nz, ny, nx = f.shape
+    flat = f.reshape(-1)
+    eps = float(np.diff(np.sort(flat)).min()) / 4
+    assert eps > 0
+    x = _dev(f).requires_grad_(True)
+    births, deaths = dms.PersistenceD0.apply(x)
+    d0_loss(births, deaths, 0.05).backward()
+    g = x.grad.cpu().numpy().reshape(-1)
+    k, j, i = np.meshgrid(np.arange(56, 72), np.arange(56, 72), np.arange(56, 72), indexing="ij")
+    sub = (i + nx * (j + ny * k)).reshape(-1)
+    nonzero = sub[g[sub] != 0]
+    zero = np.random.default_rng(51).choice(sub[g[sub] == 0], 48, replace=False)
+    assert nonzero.size > 0
+    _say("fd config5", nonzero.size, "non-zero vertices")
+
+    def loss_at(v):
+        with torch.no_grad():
+            b, d = dms.PersistenceD0.apply(_dev(v.reshape(f.shape)))
+            return float(d0_loss(b, d, 0.05))
+
+    for vid in np.concatenate([nonzero, zero]):
+        vp = flat.copy(); vp[vid] += eps
+        vm = flat.copy(); vm[vid] -= eps
+        fd = (loss_at(vp) - loss_at(vm)) / (2 * eps)
+        assert abs(fd - g[vid]) <= 1e-6 * max(abs(g[vid]), 1e-3), (int(vid), fd, g[vid])
+
+
 def test_d2_backward_config5():
     """The differentiable D2 form on the 128^3 float64 workload: births and
     deaths are the highest-vertex values of the oracle's pairs, and the
