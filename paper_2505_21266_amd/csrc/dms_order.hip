@@ -22,6 +22,8 @@
 #include "dms_internal.hpp"
 #include "dms_scan.hpp"
 
+#include <type_traits>
+
 namespace dms {
 namespace {
 
@@ -92,15 +94,30 @@ __device__ __forceinline__ void hist_add(uint32_t *h, uint32_t d, bool valid)
     if (valid && (d != d0 || lead)) atomicAdd(&h[d], lead ? (uint32_t)__popcll(same) : 1u);
 }
 
+// Element type read by a pass: the caller's values in the first pass, the
+// sort keys after.
 template <typename V, typename K, bool kFirst>
-__device__ __forceinline__ K load_key(const void *src, int64_t i, bool &nan)
+using SrcT = std::conditional_t<kFirst, V, K>;
+
+template <typename V, typename K, bool kFirst>
+__device__ __forceinline__ K to_key(SrcT<V, K, kFirst> r, bool &nan)
 {
     if constexpr (kFirst) {
-        return (K)key_of(((const V *)src)[i], nan);
+        return (K)key_of(r, nan);
     } else {
         nan = false;
-        return ((const K *)src)[i];
+        return r;
     }
+}
+
+// Loads of a tile's items are unconditional: items past the tile's end read
+// its last element (every launched tile holds at least one) and are masked
+// afterwards.  A load behind a per-item branch would make the compiler wait
+// for it before the next item's load; this way all of them are in flight at
+// once.
+__device__ __forceinline__ int64_t item_at(int64_t t0, int li, int last)
+{
+    return t0 + (li < last ? li : last);
 }
 
 // (1) per-tile histogram of the digit at `shift`; counts is digit-major:
@@ -116,39 +133,39 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t
     __shared__ uint32_t hist[kWaves][kRadix];
     __shared__ uint32_t bhist[kWaves][kRadix];
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const int64_t tile = tile_of_block(ntiles);
+    const int64_t t0 = tile * kTile;
+    const int count = tile_count(n, tile);
+    if (count == 0) return;  // block-uniform
+    const int last = count - 1;
+    using R = SrcT<V, K, kFirst>;
+    R raw[kItems];
+    uint32_t bid[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) raw[k] = ((const R *)src)[item_at(t0, local_index(wave, k, lane), last)];
+    if (ids) {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) bid[k] = ids[item_at(t0, local_index(wave, k, lane), last)];
+    }
     for (int i = tid; i < kWaves * kRadix; i += kThreads) {
         (&hist[0][0])[i] = 0;
         (&bhist[0][0])[i] = 0;
     }
     __syncthreads();
-    const int64_t tile = tile_of_block(ntiles);
-    const int64_t t0 = tile * kTile;
-    const int count = tile_count(n, tile);
     bool nan_any = false;
-    uint32_t dig[kItems];
     if (ids) {
-        uint32_t bk[kItems];
 #pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const int li = local_index(wave, k, lane);
-            bk[k] = li < count ? (ids[t0 + li] >> bshift) & (kRadix - 1) : (uint32_t)kRadix;
-        }
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) hist_add(bhist[wave], bk[k], bk[k] < (uint32_t)kRadix);
+        for (int k = 0; k < kItems; ++k)
+            hist_add(bhist[wave], (bid[k] >> bshift) & (kRadix - 1), local_index(wave, k, lane) < count);
     }
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {  // all loads first
-        const int li = local_index(wave, k, lane);
-        dig[k] = kRadix;
-        if (li < count) {
-            bool nan;
-            K key = load_key<V, K, kFirst>(src, t0 + li, nan);
-            nan_any |= nan;
-            dig[k] = (uint32_t)(key >> shift) & (kRadix - 1);
-        }
+    for (int k = 0; k < kItems; ++k) {
+        const bool valid = local_index(wave, k, lane) < count;
+        bool nan;
+        const K key = to_key<V, K, kFirst>(raw[k], nan);
+        nan_any |= valid && nan;
+        hist_add(hist[wave], (uint32_t)(key >> shift) & (kRadix - 1), valid);
     }
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) hist_add(hist[wave], dig[k], dig[k] < (uint32_t)kRadix);
     __syncthreads();
     uint32_t tot = 0;
 #pragma unroll
@@ -245,15 +262,25 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
     __shared__ Staging<K, uint32_t> S;
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const int64_t tile = tile_of_block(ntiles);
+    const int64_t t0 = tile * kTile;
+    const int count = tile_count(n, tile);
+    if (count == 0) return;  // block-uniform
+    const int last = count - 1;
+    using R = SrcT<V, K, kFirst>;
+    R raw[kItems];
+    uint32_t id[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t at = item_at(t0, local_index(wave, k, lane), last);
+        raw[k] = ((const R *)src)[at];
+        id[k] = kFirst ? (uint32_t)at : src_ids[at];
+    }
     for (int i = tid; i < kWaves * kRadix; i += kThreads) (&whist[0][0])[i] = 0;
     zero_masks(S);
     __syncthreads();
 
-    const int64_t tile = tile_of_block(ntiles);
-    const int64_t t0 = tile * kTile;
-    const int count = tile_count(n, tile);
     K key[kItems];
-    uint32_t id[kItems];
     uint32_t rank[kItems];
     // a batch tile usually lies in one field: the fields of its first and
     // last elements bound the search for the others
@@ -267,18 +294,13 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int li = local_index(wave, k, lane);
-        key[k] = 0;
-        id[k] = 0;
-        if (li < count) {
-            bool nan;
-            key[k] = load_key<V, K, kFirst>(src, t0 + li, nan);
-            if constexpr (kFirst && sizeof(K) == 8) {
-                if (foff) {
-                    const int f = f_first == f_last ? f_first : field_between(foff, f_first, f_last, t0 + li);
-                    key[k] |= (K)f << 32;
-                }
+        bool nan;
+        key[k] = to_key<V, K, kFirst>(raw[k], nan);
+        if constexpr (kFirst && sizeof(K) == 8) {
+            if (foff && li < count) {
+                const int f = f_first == f_last ? f_first : field_between(foff, f_first, f_last, t0 + li);
+                key[k] |= (K)f << 32;
             }
-            id[k] = kFirst ? (uint32_t)(t0 + li) : src_ids[t0 + li];
         }
     }
 #pragma unroll
@@ -478,20 +500,22 @@ __global__ __launch_bounds__(kThreads) void k_fine_hist(const uint32_t *pair_id,
 {
     __shared__ uint32_t hist[kWaves][kRadix];
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    for (int i = tid; i < kWaves * kRadix; i += kThreads) (&hist[0][0])[i] = 0;
-    __syncthreads();
     const int64_t c = tile_of_block(nchunks);
     const int64_t t0 = c * kTile;
     const int count = tile_count(n, c);
     const uint32_t fmask = (1u << flog) - 1u;
-    uint32_t dig[kItems];
+    uint32_t raw[kItems];
+    if (count > 0) {
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int li = local_index(wave, k, lane);
-        dig[k] = li < count ? (pair_id[t0 + li] >> fshift) & fmask : (uint32_t)kRadix;
+        for (int k = 0; k < kItems; ++k) raw[k] = pair_id[item_at(t0, local_index(wave, k, lane), count - 1)];
     }
+    for (int i = tid; i < kWaves * kRadix; i += kThreads) (&hist[0][0])[i] = 0;
+    __syncthreads();
+    if (count > 0) {
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) hist_add(hist[wave], dig[k], dig[k] < (uint32_t)kRadix);
+        for (int k = 0; k < kItems; ++k)
+            hist_add(hist[wave], (raw[k] >> fshift) & fmask, local_index(wave, k, lane) < count);
+    }
     __syncthreads();
     if (tid <= (int)fmask) {
         uint32_t tot = 0;
@@ -586,10 +610,12 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_window(const uint32_t *_
         uint32_t v[kInvUnroll];
         int32_t r[kInvUnroll];
 #pragma unroll
-        for (int u = 0; u < kInvUnroll; ++u) {
+        for (int u = 0; u < kInvUnroll; ++u) {  // unconditional loads (cnt >= 1)
             const int i = i0 + u * kInvThreads + (int)threadIdx.x;
-            v[u] = i < cnt ? pair_id[base + i] : 0xffffffffu;
-            r[u] = i < cnt ? pair_pos[base + i] : 0;
+            const int64_t at = base + (i < cnt ? i : cnt - 1);
+            v[u] = pair_id[at];
+            r[u] = pair_pos[at];
+            if (i >= cnt) v[u] = 0xffffffffu;
         }
 #pragma unroll
         for (int u = 0; u < kInvUnroll; ++u) {

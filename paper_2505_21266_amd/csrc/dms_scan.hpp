@@ -44,17 +44,23 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *total)
 }
 
 // Sum of each chunk (order-free, so the loads are striped across the block
-// and coalesced).
+// and coalesced).  Loads past the end re-read the last element and are
+// dropped, so that none waits behind a branch (every block's chunk starts
+// inside the data).
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T *in, int64_t len, T *partials)
 {
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-    T s = 0;
+    T x[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t i = base + k * kScanThreads + threadIdx.x;
-        if (i < len) s += in[i];
+        x[k] = in[i < len ? i : len - 1];
     }
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k * kScanThreads + threadIdx.x < len) s += x[k];
     T total;
     block_exclusive_scan(s, &total);
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
@@ -93,10 +99,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(T *data, int64_t len
     __shared__ T buf[kScanChunk];
     const int64_t base = (int64_t)blockIdx.x * kScanChunk;
     const int tid = threadIdx.x;
+    T x[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {  // unconditional loads, as in k_scan_reduce
+        const int64_t i = base + k * kScanThreads + tid;
+        x[k] = data[i < len ? i : len - 1];
+    }
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int j = k * kScanThreads + tid;
-        buf[j] = base + j < len ? data[base + j] : T(0);
+        buf[j] = base + j < len ? x[k] : T(0);
     }
     __syncthreads();
     T v[kScanItems];
