@@ -525,18 +525,29 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
                       z0 + S::HZ <= nz;
     bool nan = false, nan_any = false;
     if (full && nx * S::HY < (1ll << 31)) {
-        // inside the grid: a plane base per halo plane (uniform) and a 32-bit
+        // inside the grid: each thread issues a fixed number of loads (its
+        // last one clamped into the halo) before any LDS store, so that all
+        // are in flight at once; a 64-bit base per halo plane and a 32-bit
         // offset within the plane
+        static_assert(S::HZ == 3, "three halo planes");
         constexpr int kPlane = S::HX * S::HY;
+        constexpr int kPer = (S::kHalo + kThreads - 1) / kThreads;
         const int nxi = (int)nx;
+        const int64_t base0 = x0 + nx * (y0 + ny * z0), pstride = nx * ny;
+        typename Keys::H hv[kPer];
 #pragma unroll
-        for (int hz = 0; hz < S::HZ; ++hz) {
-            const int64_t base = x0 + nx * (y0 + ny * (z0 + hz));
-            for (int i = tid; i < kPlane; i += kThreads) {
-                const int hy = i / S::HX, hx = i - hy * S::HX;
-                tile[hz * kPlane + i] = Keys::load(field, base + hx + hy * nxi, nan);
-                nan_any |= nan;
-            }
+        for (int j = 0; j < kPer; ++j) {
+            const int i = min(tid + j * kThreads, S::kHalo - 1);
+            const int hz = i / kPlane, r = i - hz * kPlane;
+            const int hy = r / S::HX, hx = r - hy * S::HX;
+            const int64_t pb = hz == 0 ? base0 : (hz == 1 ? base0 + pstride : base0 + 2 * pstride);
+            hv[j] = Keys::load(field, pb + hx + hy * nxi, nan);
+            nan_any |= nan;
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = tid + j * kThreads;
+            if (i < S::kHalo) tile[i] = hv[j];
         }
     } else {
         for (int i = tid; i < S::kHalo; i += kThreads) {
