@@ -32,6 +32,15 @@ constexpr int kWaves = kThreads / kWave;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;
 constexpr int kRadix = 256;
+// The histogram and scatter of every pass but the last run 512-thread blocks
+// (8192-key tiles) for 4-byte keys: a tile's run of one digit is then about
+// 32 keys, a whole 128-byte line, and the scattered writes cost less (about
+// 0.1 ms per histogram and 0.5-0.7 ms per scatter at 2^30 keys).  The last
+// pass (two rankings, more registers) and 8-byte keys keep 256 threads: two
+// 512-thread blocks of those would not fit one CU's registers.
+constexpr int kWideThreads = 512;
+template <typename K>
+constexpr int pass_threads() { return sizeof(K) == 4 ? kWideThreads : kThreads; }
 
 // Key types: uint32_t for float32, uint64_t for float64 and for batches
 // (field index in bits 32..39 above the float32 key).
@@ -72,10 +81,11 @@ __device__ __forceinline__ int local_index(int wave, int k, int lane)
     return wave * (kItems * kWave) + k * kWave + lane;
 }
 
+template <int kT = kTile>
 __device__ __forceinline__ int tile_count(int64_t n, int64_t tile)
 {
-    const int64_t left = n - tile * kTile;
-    return left <= 0 ? 0 : (left < kTile ? (int)left : kTile);
+    const int64_t left = n - tile * kT;
+    return left <= 0 ? 0 : (left < kT ? (int)left : kT);
 }
 
 // Histogram update for one item per lane (counts only, no ranks), one LDS
@@ -124,18 +134,19 @@ __device__ __forceinline__ int64_t item_at(int64_t t0, int li, int last)
 // counts[d * ntiles + tile].
 // With ids != null (the last pass) it also histograms the vertex ids by
 // bucket (id >> bshift) into bcounts, for the grouped inversion.
-template <typename V, typename K, bool kFirst>
-__global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t n, int shift,
+template <typename V, typename K, bool kFirst, int kThr>
+__global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, int shift,
                                                         uint32_t *counts, int64_t ntiles,
                                                         uint32_t *flags, const uint32_t *ids,
                                                         int bshift, uint32_t *bcounts)
 {
-    __shared__ uint32_t hist[kWaves][kRadix];
-    __shared__ uint32_t bhist[kWaves][kRadix];
+    constexpr int kW = kThr / kWave;
+    __shared__ uint32_t hist[kW][kRadix];
+    __shared__ uint32_t bhist[kW][kRadix];
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int64_t tile = tile_of_block(ntiles);
-    const int64_t t0 = tile * kTile;
-    const int count = tile_count(n, tile);
+    const int64_t t0 = tile * (kThr * kItems);
+    const int count = tile_count<kThr * kItems>(n, tile);
     if (count == 0) return;  // block-uniform
     const int last = count - 1;
     using R = SrcT<V, K, kFirst>;
@@ -147,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t
 #pragma unroll
         for (int k = 0; k < kItems; ++k) bid[k] = ids[item_at(t0, local_index(wave, k, lane), last)];
     }
-    for (int i = tid; i < kWaves * kRadix; i += kThreads) {
+    for (int i = tid; i < kW * kRadix; i += kThr) {
         (&hist[0][0])[i] = 0;
         (&bhist[0][0])[i] = 0;
     }
@@ -167,17 +178,18 @@ __global__ __launch_bounds__(kThreads) void k_tile_hist(const void *src, int64_t
         hist_add(hist[wave], (uint32_t)(key >> shift) & (kRadix - 1), valid);
     }
     __syncthreads();
+    if (kFirst && __ballot(nan_any) && lane == 0) atomicOr(flags, (uint32_t)DMS_FLAG_NAN);
+    if (tid >= kRadix) return;  // a thread per digit
     uint32_t tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) tot += hist[w][tid];
+    for (int w = 0; w < kW; ++w) tot += hist[w][tid];
     counts[(int64_t)tid * ntiles + tile] = tot;  // digit-major, tiles in tile order
     if (ids) {
         uint32_t bt = 0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) bt += bhist[w][tid];
+        for (int w = 0; w < kW; ++w) bt += bhist[w][tid];
         bcounts[(int64_t)tid * ntiles + tile] = bt;
     }
-    if (kFirst && __ballot(nan_any) && lane == 0) atomicOr(flags, (uint32_t)DMS_FLAG_NAN);
 }
 
 // Rank of an item among the wave's items with the same 8-bit digit, counting
@@ -212,15 +224,18 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t *
     return base + below;
 }
 
-// Thread tid owns digit tid: the per-wave counts become exclusive prefixes
-// over the waves; returns the tile's count of the digit.
+// Thread tid < kRadix owns digit tid: the per-wave counts become exclusive
+// prefixes over the waves; returns the tile's count of the digit (0 on the
+// other threads).
+template <int kThr = kThreads>
 __device__ __forceinline__ uint32_t wave_prefix(uint32_t (*wh)[kRadix])
 {
-    static_assert(kRadix == kThreads, "one thread per digit");
+    static_assert(kThr >= kRadix, "a thread per digit");
     const int tid = threadIdx.x;
+    if (tid >= kRadix) return 0;
     uint32_t run = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < kThr / kWave; ++w) {
         const uint32_t c = wh[w][tid];
         wh[w][tid] = run;
         run += c;
@@ -234,37 +249,38 @@ __device__ __forceinline__ uint32_t wave_prefix(uint32_t (*wh)[kRadix])
 // the field index above the value key.
 // LDS staging of a tile; the digit masks of the ranking phase live in the
 // same bytes (the phases are separated by a barrier).
-template <typename A, typename B>
+template <typename A, typename B, int kThr = kThreads>
 union Staging {
     struct {
-        A a[kTile];
-        B b[kTile];
+        A a[kThr * kItems];
+        B b[kThr * kItems];
     } st;
-    uint64_t mk[kWaves][kRadix];
+    uint64_t mk[kThr / kWave][kRadix];
 };
 
-template <typename A, typename B>
-__device__ __forceinline__ void zero_masks(Staging<A, B> &S)
+template <typename A, typename B, int kThr>
+__device__ __forceinline__ void zero_masks(Staging<A, B, kThr> &S)
 {
-    for (int i = threadIdx.x; i < kWaves * kRadix; i += kThreads) (&S.mk[0][0])[i] = 0ull;
+    for (int i = threadIdx.x; i < (kThr / kWave) * kRadix; i += kThr) (&S.mk[0][0])[i] = 0ull;
 }
 
-template <typename V, typename K, bool kFirst>
-__global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uint32_t *src_ids,
+template <typename V, typename K, bool kFirst, int kThr>
+__global__ __launch_bounds__(kThr) void k_scatter(const void *src, const uint32_t *src_ids,
                                                       int64_t n, int shift,
                                                       const uint32_t *offsets, int64_t ntiles,
                                                       K *dst_keys, uint32_t *dst_ids,
                                                       const int64_t *foff, int nfields)
 {
-    __shared__ uint32_t whist[kWaves][kRadix];
+    constexpr int kW = kThr / kWave;
+    __shared__ uint32_t whist[kW][kRadix];
     __shared__ uint32_t digit_start[kRadix];
     __shared__ uint32_t gbase[kRadix];
-    __shared__ Staging<K, uint32_t> S;
+    __shared__ Staging<K, uint32_t, kThr> S;
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int64_t tile = tile_of_block(ntiles);
-    const int64_t t0 = tile * kTile;
-    const int count = tile_count(n, tile);
+    const int64_t t0 = tile * (kThr * kItems);
+    const int count = tile_count<kThr * kItems>(n, tile);
     if (count == 0) return;  // block-uniform
     const int last = count - 1;
     using R = SrcT<V, K, kFirst>;
@@ -276,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
         raw[k] = ((const R *)src)[at];
         id[k] = kFirst ? (uint32_t)at : src_ids[at];
     }
-    for (int i = tid; i < kWaves * kRadix; i += kThreads) (&whist[0][0])[i] = 0;
+    for (int i = tid; i < kW * kRadix; i += kThr) (&whist[0][0])[i] = 0;
     zero_masks(S);
     __syncthreads();
 
@@ -310,11 +326,13 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
     __syncthreads();
     {
         uint32_t total;
-        const uint32_t start = block_exclusive_scan<uint32_t>(wave_prefix(whist), &total);
-        digit_start[tid] = start;
+        const uint32_t start = block_exclusive_scan<uint32_t, kThr>(wave_prefix<kThr>(whist), &total);
         // global position of the tile's element at local position p of digit d:
         // gbase[d] + p (gbase holds the scanned offset minus the local start)
-        gbase[tid] = offsets[(int64_t)tid * ntiles + tile] - start;
+        if (tid < kRadix) {
+            digit_start[tid] = start;
+            gbase[tid] = offsets[(int64_t)tid * ntiles + tile] - start;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -329,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const void *src, const uin
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        const int p = tid + j * kThreads;
+        const int p = tid + j * kThr;
         if (p < count) {
             const K kk = S.st.a[p];
             const uint32_t g = gbase[(uint32_t)(kk >> shift) & (kRadix - 1)] + (uint32_t)p;
@@ -661,6 +679,8 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
     const OrderLayout L = order_layout<K>(n);
     const InvertPlan P = invert_plan(n);
     const int64_t ntiles = (n + kTile - 1) / kTile;
+    constexpr int kWide = pass_threads<K>();
+    const int64_t nwide = (n + kWide * kItems - 1) / (kWide * kItems);
     K *keys[2] = {(K *)(ws + L.keys0), (K *)(ws + L.keys1)};
     uint32_t *ids[2] = {(uint32_t *)(ws + L.ids0), (uint32_t *)(ws + L.ids1)};
     uint32_t *counts = (uint32_t *)(ws + L.counts);
@@ -668,27 +688,31 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
     uint32_t *bcounts = (uint32_t *)(ws + L.bcounts);
     uint32_t *bpartials = (uint32_t *)(ws + L.bpartials);
     const dim3 grid((unsigned)ntiles), block(kThreads);
+    const dim3 wgrid((unsigned)nwide), wblock(kWide);
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         const bool last = p == passes - 1;
         const void *src = p == 0 ? values : (const void *)keys[(p - 1) & 1];
         const uint32_t *sids = p == 0 ? nullptr : ids[(p - 1) & 1];
-        if (p == 0)
-            hipLaunchKernelGGL((k_tile_hist<V, K, true>), grid, block, 0, s, src, n, shift, counts,
-                               ntiles, flags, nullptr, 0, nullptr);
-        else
-            hipLaunchKernelGGL((k_tile_hist<V, K, false>), grid, block, 0, s, src, n, shift, counts,
-                               ntiles, flags, last ? sids : nullptr, P.bshift, bcounts);
-        exclusive_scan<uint32_t>(counts, ntiles * kRadix, partials, s);
         if (!last) {
-            if (p == 0)
-                hipLaunchKernelGGL((k_scatter<V, K, true>), grid, block, 0, s, src, sids, n, shift,
-                                   counts, ntiles, keys[p & 1], ids[p & 1], foff, nfields);
-            else
-                hipLaunchKernelGGL((k_scatter<V, K, false>), grid, block, 0, s, src, sids, n, shift,
-                                   counts, ntiles, keys[p & 1], ids[p & 1], foff, nfields);
+            if (p == 0) {
+                hipLaunchKernelGGL((k_tile_hist<V, K, true, kWide>), wgrid, wblock, 0, s, src, n, shift,
+                                   counts, nwide, flags, nullptr, 0, nullptr);
+                exclusive_scan<uint32_t>(counts, nwide * kRadix, partials, s);
+                hipLaunchKernelGGL((k_scatter<V, K, true, kWide>), wgrid, wblock, 0, s, src, sids, n, shift,
+                                   counts, nwide, keys[p & 1], ids[p & 1], foff, nfields);
+            } else {
+                hipLaunchKernelGGL((k_tile_hist<V, K, false, kWide>), wgrid, wblock, 0, s, src, n, shift,
+                                   counts, nwide, flags, nullptr, 0, nullptr);
+                exclusive_scan<uint32_t>(counts, nwide * kRadix, partials, s);
+                hipLaunchKernelGGL((k_scatter<V, K, false, kWide>), wgrid, wblock, 0, s, src, sids, n,
+                                   shift, counts, nwide, keys[p & 1], ids[p & 1], foff, nfields);
+            }
             continue;
         }
+        hipLaunchKernelGGL((k_tile_hist<V, K, false, kThreads>), grid, block, 0, s, src, n, shift, counts,
+                           ntiles, flags, sids, P.bshift, bcounts);
+        exclusive_scan<uint32_t>(counts, ntiles * kRadix, partials, s);
         exclusive_scan<uint32_t>(bcounts, ntiles * kRadix, bpartials, s);
         // level 0 into the free buffers; level 1 back into the last pass's
         // source buffers once they are read

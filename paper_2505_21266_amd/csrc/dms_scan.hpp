@@ -22,19 +22,19 @@ __device__ __forceinline__ T wave_inclusive_scan(T v)
     return v;
 }
 
-// Exclusive scan of one value per thread over a 256-thread block; returns the
-// exclusive prefix, writes the block total to *total.
-template <typename T>
+// Exclusive scan of one value per thread over a kBlock-thread block; returns
+// the exclusive prefix, writes the block total to *total.
+template <typename T, int kBlock = kScanThreads>
 __device__ __forceinline__ T block_exclusive_scan(T v, T *total)
 {
-    __shared__ T wsum[kScanThreads / kWave];
+    __shared__ T wsum[kBlock / kWave];
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     T inc = wave_inclusive_scan(v);
     if (lane == kWave - 1) wsum[wave] = inc;
     __syncthreads();
     T before = 0, all = 0;
 #pragma unroll
-    for (int w = 0; w < kScanThreads / kWave; ++w) {
+    for (int w = 0; w < kBlock / kWave; ++w) {
         if (w < wave) before += wsum[w];
         all += wsum[w];
     }
