@@ -74,6 +74,15 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t ntiles)
 }
 
 
+// The value as computed at this point: an empty asm statement that the
+// compiler must treat as reading and rewriting the register, so the
+// computation cannot move below it.
+__device__ __forceinline__ uint32_t settled(uint32_t v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // Element k of this lane in its tile (wave-striped), as an offset from the
 // tile's first element.
 __device__ __forceinline__ int local_index(int wave, int k, int lane)
@@ -202,8 +211,8 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
 // instructions, which pays where the vector units are the busier resource
 // (measured per pass).  A wave whose lanes share one digit (the high bytes of
 // a smooth field) skips either.
-template <bool kLds>
-__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t *wh, uint64_t *mk)
+template <bool kLds, typename CT>
+__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, CT *wh, uint64_t *mk)
 {
     const uint64_t act = __ballot(valid);
     const uint32_t d0 = __builtin_amdgcn_readfirstlane(valid ? d : 0xffffffffu);
@@ -220,15 +229,15 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t *
     uint32_t base = 0;
     if (valid) base = wh[d];
     const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
-    if (valid && below == 0) wh[d] = base + (uint32_t)__popcll(peers);
+    if (valid && below == 0) wh[d] = (CT)(base + (uint32_t)__popcll(peers));
     return base + below;
 }
 
 // Thread tid < kRadix owns digit tid: the per-wave counts become exclusive
 // prefixes over the waves; returns the tile's count of the digit (0 on the
 // other threads).
-template <int kThr = kThreads>
-__device__ __forceinline__ uint32_t wave_prefix(uint32_t (*wh)[kRadix])
+template <int kThr = kThreads, typename CT>
+__device__ __forceinline__ uint32_t wave_prefix(CT (*wh)[kRadix])
 {
     static_assert(kThr >= kRadix, "a thread per digit");
     const int tid = threadIdx.x;
@@ -237,7 +246,7 @@ __device__ __forceinline__ uint32_t wave_prefix(uint32_t (*wh)[kRadix])
 #pragma unroll
     for (int w = 0; w < kThr / kWave; ++w) {
         const uint32_t c = wh[w][tid];
-        wh[w][tid] = run;
+        wh[w][tid] = (CT)run;
         run += c;
     }
     return run;
@@ -413,6 +422,8 @@ InvertPlan invert_plan(int64_t n)
 // and staged in LDS in bucket order, so that a bucket's pairs from this tile
 // leave as one contiguous run at the bucket's scanned offset (boffsets).
 // For batches the position is taken relative to the field's first vertex.
+// Per-wave counts are 16-bit (at most kTile), so that the block's LDS stays
+// just under 40 KiB and four blocks share a CU.
 template <typename K>
 __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const uint32_t *src_ids,
                                                            int64_t n, int shift,
@@ -421,8 +432,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
                                                            const int64_t *foff, int bshift,
                                                            uint32_t *pair_id, int32_t *pair_pos)
 {
-    __shared__ uint32_t dwh[kWaves][kRadix];
-    __shared__ uint32_t bwh[kWaves][kRadix];
+    __shared__ uint16_t dwh[kWaves][kRadix];
+    __shared__ uint16_t bwh[kWaves][kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t bstart[kRadix];
     __shared__ uint32_t bbase[kRadix];
@@ -439,26 +450,30 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
     const int64_t tile = tile_of_block(ntiles);
     const int64_t t0 = tile * kTile;
     const int count = tile_count(n, tile);
-    // per item after the ranking: id, (digit rank | digit << 16) and
-    // (bucket rank | field << 16); ranks are below kTile = 2^12
-    uint32_t id[kItems], dr[kItems], br[kItems];
+    if (count == 0) return;  // block-uniform
+    // per item after the ranking: the id and, packed, its digit rank and its
+    // bucket rank inside the wave (each below 16 x 64 = 2^10) and its digit;
+    // batches also keep the field
+    uint32_t id[kItems], pk[kItems];
+    uint32_t fld[sizeof(K) == 8 ? kItems : 1];
     {
         K key[kItems];
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
-            const int li = local_index(wave, k, lane);
-            const bool valid = li < count;
-            key[k] = valid ? src[t0 + li] : K(0);
-            id[k] = valid ? src_ids[t0 + li] : 0u;
+            const int64_t at = item_at(t0, local_index(wave, k, lane), count - 1);
+            key[k] = src[at];
+            id[k] = src_ids[at];
         }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const bool valid = local_index(wave, k, lane) < count;
             const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-            dr[k] = wave_rank<true>(d, valid, dwh[wave], S.mk[wave]) | d << 16;
-            uint32_t field = 0;
-            if constexpr (sizeof(K) == 8) field = (uint32_t)(key[k] >> 32);
-            br[k] = wave_rank<true>((id[k] >> bshift) & (kRadix - 1), valid, bwh[wave], S.mk[wave]) | field << 16;
+            const uint32_t rd = wave_rank<true>(d, valid, dwh[wave], S.mk[wave]);
+            const uint32_t rb = wave_rank<true>((id[k] >> bshift) & (kRadix - 1), valid, bwh[wave], S.mk[wave]);
+            // settled here: otherwise the compiler sinks the rank popcounts past
+            // the barrier and keeps every item's two 64-bit lane masks alive
+            pk[k] = settled(rd | d << 10 | rb << 18);
+            if constexpr (sizeof(K) == 8) fld[k] = (uint32_t)(key[k] >> 32);
         }
     }
     __syncthreads();
@@ -474,14 +489,14 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         if (local_index(wave, k, lane) < count) {
-            const uint32_t d = dr[k] >> 16;
+            const uint32_t d = (pk[k] >> 10) & (kRadix - 1);
             const uint32_t b = (id[k] >> bshift) & (kRadix - 1);
-            const int64_t g = (int64_t)gbase[d] + dwh[wave][d] + (dr[k] & 0xffffu);
+            const int64_t g = (int64_t)gbase[d] + dwh[wave][d] + (pk[k] & 1023u);
             int64_t base = 0;
             if constexpr (sizeof(K) == 8) {
-                if (foff) base = foff[br[k] >> 16];
+                if (foff) base = foff[fld[k]];
             }
-            const uint32_t pos = bstart[b] + bwh[wave][b] + (br[k] & 0xffffu);
+            const uint32_t pos = bstart[b] + bwh[wave][b] + (pk[k] >> 18);
             if (pos < (uint32_t)kTile) {
                 S.st.a[pos] = id[k];
                 S.st.b[pos] = (int32_t)(g - base);
