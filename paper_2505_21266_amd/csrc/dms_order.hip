@@ -209,8 +209,9 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
 // the wave's mask slot of its digit (mk, zero between uses), reads the slot
 // back and clears it -- three LDS operations in place of some forty vector
 // instructions, which pays where the vector units are the busier resource
-// (measured per pass).  A wave whose lanes share one digit (the high bytes of
-// a smooth field) skips either.
+// (measured per kernel: the radix scatters use LDS, the fine partition the
+// ballots).  A wave whose lanes share one digit (the high bytes of a smooth
+// field) skips either.
 template <bool kLds, typename CT>
 __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, CT *wh, uint64_t *mk)
 {
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(kThr) void k_scatter(const void *src, const uint32_
     }
 #pragma unroll
     for (int k = 0; k < kItems; ++k)
-        rank[k] = wave_rank<!kFirst>((uint32_t)(key[k] >> shift) & (kRadix - 1),
+        rank[k] = wave_rank<true>((uint32_t)(key[k] >> shift) & (kRadix - 1),
                                      local_index(wave, k, lane) < count, whist[wave], S.mk[wave]);
     __syncthreads();
     {
