@@ -32,12 +32,12 @@ constexpr int kWaves = kThreads / kWave;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;
 constexpr int kRadix = 256;
-// The histogram and scatter of every pass but the last run 512-thread blocks
-// (8192-key tiles) for 4-byte keys: a tile's run of one digit is then about
-// 32 keys, a whole 128-byte line, and the scattered writes cost less (about
-// 0.1 ms per histogram and 0.5-0.7 ms per scatter at 2^30 keys).  The last
-// pass (two rankings, more registers) and 8-byte keys keep 256 threads: two
-// 512-thread blocks of those would not fit one CU's registers.
+// The radix passes run 512-thread blocks (8192-key tiles) for 4-byte keys: a
+// tile's run of one digit (or, in the last pass, of one id bucket) is then
+// about 32 keys, a whole 128-byte line, and the scattered writes cost less
+// (about 0.1 ms per histogram and 0.5-0.7 ms per scatter at 2^30 keys).
+// 8-byte keys keep 256 threads: two 512-thread blocks of those would not fit
+// one CU's LDS and registers.  The fine partition of the inversion keeps 256.
 constexpr int kWideThreads = 512;
 template <typename K>
 constexpr int pass_threads() { return sizeof(K) == 4 ? kWideThreads : kThreads; }
@@ -423,25 +423,27 @@ InvertPlan invert_plan(int64_t n)
 // and staged in LDS in bucket order, so that a bucket's pairs from this tile
 // leave as one contiguous run at the bucket's scanned offset (boffsets).
 // For batches the position is taken relative to the field's first vertex.
-// Per-wave counts are 16-bit (at most kTile), so that the block's LDS stays
-// just under 40 KiB and four blocks share a CU.
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const uint32_t *src_ids,
+// Per-wave counts are 16-bit (at most a tile), so that the block's LDS stays
+// just under 40 KiB at 256 threads (four blocks per CU) and 75 KiB at 512
+// (two).
+template <typename K, int kThr>
+__global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint32_t *src_ids,
                                                            int64_t n, int shift,
                                                            const uint32_t *offsets,
                                                            const uint32_t *boffsets, int64_t ntiles,
                                                            const int64_t *foff, int bshift,
                                                            uint32_t *pair_id, int32_t *pair_pos)
 {
-    __shared__ uint16_t dwh[kWaves][kRadix];
-    __shared__ uint16_t bwh[kWaves][kRadix];
+    constexpr int kW = kThr / kWave, kT = kThr * kItems;
+    __shared__ uint16_t dwh[kW][kRadix];
+    __shared__ uint16_t bwh[kW][kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t bstart[kRadix];
     __shared__ uint32_t bbase[kRadix];
-    __shared__ Staging<uint32_t, int32_t> S;
+    __shared__ Staging<uint32_t, int32_t, kThr> S;
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    for (int i = tid; i < kWaves * kRadix; i += kThreads) {
+    for (int i = tid; i < kW * kRadix; i += kThr) {
         (&dwh[0][0])[i] = 0;
         (&bwh[0][0])[i] = 0;
     }
@@ -449,8 +451,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
     __syncthreads();
 
     const int64_t tile = tile_of_block(ntiles);
-    const int64_t t0 = tile * kTile;
-    const int count = tile_count(n, tile);
+    const int64_t t0 = tile * kT;
+    const int count = tile_count<kT>(n, tile);
     if (count == 0) return;  // block-uniform
     // per item after the ranking: the id and, packed, its digit rank and its
     // bucket rank inside the wave (each below 16 x 64 = 2^10) and its digit;
@@ -479,12 +481,14 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
     }
     __syncthreads();
     {
-        wave_prefix(dwh);
+        wave_prefix<kThr>(dwh);
         uint32_t total;
-        const uint32_t start = block_exclusive_scan<uint32_t>(wave_prefix(bwh), &total);
-        bstart[tid] = start;
-        gbase[tid] = offsets[(int64_t)tid * ntiles + tile];
-        bbase[tid] = boffsets[(int64_t)tid * ntiles + tile] - start;
+        const uint32_t start = block_exclusive_scan<uint32_t, kThr>(wave_prefix<kThr>(bwh), &total);
+        if (tid < kRadix) {
+            bstart[tid] = start;
+            gbase[tid] = offsets[(int64_t)tid * ntiles + tile];
+            bbase[tid] = boffsets[(int64_t)tid * ntiles + tile] - start;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
                 if (foff) base = foff[fld[k]];
             }
             const uint32_t pos = bstart[b] + bwh[wave][b] + (pk[k] >> 18);
-            if (pos < (uint32_t)kTile) {
+            if (pos < (uint32_t)kT) {
                 S.st.a[pos] = id[k];
                 S.st.b[pos] = (int32_t)(g - base);
             }
@@ -507,7 +511,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter_last(const K *src, const u
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        const int p = tid + j * kThreads;
+        const int p = tid + j * kThr;
         if (p < count) {
             const uint32_t who = S.st.a[p];
             const uint32_t dst = bbase[(who >> bshift) & (kRadix - 1)] + (uint32_t)p;
@@ -703,7 +707,7 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
     uint32_t *partials = (uint32_t *)(ws + L.partials);
     uint32_t *bcounts = (uint32_t *)(ws + L.bcounts);
     uint32_t *bpartials = (uint32_t *)(ws + L.bpartials);
-    const dim3 grid((unsigned)ntiles), block(kThreads);
+    const dim3 block(kThreads);
     const dim3 wgrid((unsigned)nwide), wblock(kWide);
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
@@ -726,16 +730,16 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
             }
             continue;
         }
-        hipLaunchKernelGGL((k_tile_hist<V, K, false, kThreads>), grid, block, 0, s, src, n, shift, counts,
-                           ntiles, flags, sids, P.bshift, bcounts);
-        exclusive_scan<uint32_t>(counts, ntiles * kRadix, partials, s);
-        exclusive_scan<uint32_t>(bcounts, ntiles * kRadix, bpartials, s);
+        hipLaunchKernelGGL((k_tile_hist<V, K, false, kWide>), wgrid, wblock, 0, s, src, n, shift, counts,
+                           nwide, flags, sids, P.bshift, bcounts);
+        exclusive_scan<uint32_t>(counts, nwide * kRadix, partials, s);
+        exclusive_scan<uint32_t>(bcounts, nwide * kRadix, bpartials, s);
         // level 0 into the free buffers; level 1 back into the last pass's
         // source buffers once they are read
         uint32_t *aid = (uint32_t *)keys[p & 1];
         int32_t *apos = (int32_t *)ids[p & 1];
-        hipLaunchKernelGGL((k_scatter_last<K>), grid, block, 0, s, (const K *)src, sids, n, shift,
-                           counts, bcounts, ntiles, foff, P.bshift, aid, apos);
+        hipLaunchKernelGGL((k_scatter_last<K, kWide>), wgrid, wblock, 0, s, (const K *)src, sids, n, shift,
+                           counts, bcounts, nwide, foff, P.bshift, aid, apos);
         if (P.fine) {
             uint32_t *fid = (uint32_t *)keys[(p - 1) & 1];
             int32_t *fpos = (int32_t *)ids[(p - 1) & 1];

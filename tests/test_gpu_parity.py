@@ -54,7 +54,9 @@ def _field(dims, kind, seed):
 
 # ----------------------------------------------------------------- order
 
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 12289, 100003])
+# 4096 and 8192 are the tile sizes of the last pass and of the float32
+# passes before it; sizes around them leave one-item and one-short tiles
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 12289, 16385, 100003])
 @pytest.mark.parametrize("kind", ["noise", "ties"])
 def test_order_sizes(n, kind):
     rng = np.random.default_rng(n)
@@ -82,10 +84,14 @@ def test_order_special_values(dtype):
     assert (got == oracle.order(v)).all()
 
 
+# a NaN in the first and in the second half of an 8192-key tile (the halves
+# are read by different threads of a 512-thread block), at a tile's last
+# element, and in the ragged last tile
+@pytest.mark.parametrize("at", [17, 4321, 8191, 8999])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_order_nan_flag(dtype):
+def test_order_nan_flag(dtype, at):
     v = np.random.default_rng(3).random(9000).astype(dtype)
-    v[4321] = np.nan
+    v[at] = np.nan
     with pytest.raises(ValueError):
         dms.order(_dev(v))
 
