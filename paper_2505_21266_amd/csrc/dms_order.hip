@@ -14,10 +14,11 @@
 //
 // Each pass: (1) per-tile digit histograms (LDS atomics), (2) a device-wide
 // exclusive scan of the digit-major histogram matrix, (3) a stable per-tile
-// scatter.  Tiles
-// hold 4096 keys (256 threads x 16 items, wave-striped so that a wave's items
-// are in element order); ranks inside a wave come from ballot-based digit
-// matching, ranks across waves from per-wave digit counts in LDS.
+// scatter.  A tile holds 16 items per thread (8192 keys in 512-thread blocks
+// for 4-byte keys, 4096 in 256-thread blocks for 8-byte keys), wave-striped
+// so that a wave's items are in element order; ranks inside a wave come from
+// digit matching (LDS lane masks or ballots), ranks across waves from
+// per-wave digit counts in LDS.
 #include "dms_common.hpp"
 #include "dms_internal.hpp"
 #include "dms_scan.hpp"
@@ -209,8 +210,8 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
 // the wave's mask slot of its digit (mk, zero between uses), reads the slot
 // back and clears it -- three LDS operations in place of some forty vector
 // instructions, which pays where the vector units are the busier resource
-// (measured per kernel: the radix scatters use LDS, the fine partition the
-// ballots).  A wave whose lanes share one digit (the high bytes of a smooth
+// (measured per kernel: the radix scatters and the id buckets use LDS, the
+// last pass's digit and the fine partition the ballots).  A wave whose lanes share one digit (the high bytes of a smooth
 // field) skips either.
 template <bool kLds, typename CT>
 __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, CT *wh, uint64_t *mk)
@@ -471,7 +472,9 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
         for (int k = 0; k < kItems; ++k) {
             const bool valid = local_index(wave, k, lane) < count;
             const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-            const uint32_t rd = wave_rank<true>(d, valid, dwh[wave], S.mk[wave]);
+            // the top byte (sign and exponent) takes few values: ballots match
+            // it faster than the LDS masks, which serve the random id buckets
+            const uint32_t rd = wave_rank<false>(d, valid, dwh[wave], S.mk[wave]);
             const uint32_t rb = wave_rank<true>((id[k] >> bshift) & (kRadix - 1), valid, bwh[wave], S.mk[wave]);
             // settled here: otherwise the compiler sinks the rank popcounts past
             // the barrier and keeps every item's two 64-bit lane masks alive
