@@ -156,6 +156,13 @@ __device__ __forceinline__ void load_edge_tris(EdgeTris &E)
 
 // Writes the critical cells of one record (counts c, first slots at) as
 // codes base | local index.
+// kConstBits: the head tet of a triangle comes from a per-lane choice
+// between two constant bits instead of between two table entries, which the
+// compiler turns into a load it waits for.  Measured per kernel: the batched
+// fill (dense tiles of noise fields) gains, while the single-field fill
+// keeps the table form, whose lower register count keeps more of its
+// mostly one-wave candidate blocks resident.
+template <bool kConstBits>
 __device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint32_t *c,
                                             const uint64_t *at, int64_t base, const EdgeTris &E,
                                             int64_t *crit0, int64_t *crit1, int64_t *crit2,
@@ -181,7 +188,12 @@ __device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint
         const uint32_t g = tri_field(lo, hi, t);
         if (g) {
             tail_t |= 1ull << t;
-            head_q |= 1u << (g == 1 ? kTables.tri_tets[t][0] : kTables.tri_tets[t][1]);
+            if constexpr (kConstBits) {
+                const uint32_t q0 = 1u << kTables.tri_tets[t][0], q1 = 1u << kTables.tri_tets[t][1];
+                head_q |= g == 1 ? q0 : q1;
+            } else {
+                head_q |= 1u << (g == 1 ? kTables.tri_tets[t][0] : kTables.tri_tets[t][1]);
+            }
         }
     }
     const uint64_t crit_t = lower_tris(low) & ~head_t & ~tail_t;
@@ -331,7 +343,8 @@ __device__ __forceinline__ void fill_tile_full(
 #pragma unroll
         for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
         const int64_t v = box_vertex(r0 + k, w0, w1, lo0, lo1, lo2, nx, ny);
-        write_codes(lo[k], hi[k], c, at[k], v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+        write_codes<false>(lo[k], hi[k], c, at[k], v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2,
+                           cap3);
     }
 }
 
@@ -387,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill(
         c[d] = lane16(pk, d);
     }
     const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
-    write_codes(lo, hi, c, at, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+    write_codes<false>(lo, hi, c, at, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 }
 
 __global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *counts, int64_t cap0,
@@ -446,8 +459,8 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
             uint32_t c[4];
 #pragma unroll
             for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
-            write_codes(lo[k], hi[k], c, at[k], (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1,
-                        cap2, cap3);
+            write_codes<true>(lo[k], hi[k], c, at[k], (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0,
+                              cap1, cap2, cap3);
         }
         return;
     }
@@ -483,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
         c[d] = lane16(pk, d);
     }
     const int f = record_field(so, nfields, r);
-    write_codes(lo, hi, c, at, (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+    write_codes<true>(lo, hi, c, at, (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 }
 
 // First slot of every field in every list: the scanned count of its first
