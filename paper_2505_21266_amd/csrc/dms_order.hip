@@ -44,8 +44,18 @@ template <typename K>
 constexpr int pass_threads() { return sizeof(K) == 4 ? kWideThreads : kThreads; }
 
 // Key types: uint32_t for float32, uint64_t for float64 and for batches
-// (field index in bits 32..39 above the float32 key).
-constexpr int kBatchPasses = 5;
+// (field index from bit 32 up, above the float32 key): a batch sorts the four
+// value bytes and then as many bytes of the field index as the number of
+// fields needs.
+__host__ __device__ constexpr int batch_passes(int nfields)
+{
+    int p = 4;
+    for (int64_t span = 1; span < nfields; span <<= 8) ++p;
+    return p < 5 ? 5 : p;
+}
+static_assert(batch_passes(1) == 5 && batch_passes(256) == 5 && batch_passes(257) == 6 &&
+                  batch_passes(kMaxBatchFields) == 6,
+              "field bytes sorted by a batch");
 
 // field of element i: the last f in [lo, hi] with foff[f] <= i (binary
 // search; the caller knows i lies in one of fields lo..hi)
@@ -785,7 +795,7 @@ int launch_order_batch(const float *values, int64_t n, const int64_t *foff, int 
                        int32_t *order, char *ws, uint32_t *flags, hipStream_t s)
 {
     if (n == 0) return DMS_OK;
-    return run_order<float, uint64_t>(values, n, kBatchPasses, order, ws, flags, foff, nfields, s);
+    return run_order<float, uint64_t>(values, n, batch_passes(nfields), order, ws, flags, foff, nfields, s);
 }
 
 }  // namespace dms

@@ -63,6 +63,18 @@ def test_batch_exact_per_field():
     _check_fields(SIDES, fields, *out)
 
 
+def test_batch_many_fields():
+    """More fields than one byte can index: the sort must group by the whole
+    field index (a second field byte), or fields f and f + 256 would mix."""
+    rng = np.random.default_rng(77)
+    sides = [tuple(int(x) for x in rng.integers(1, 7, 3)) for _ in range(300)]
+    fields = [_field(s, i % 3, 900 + i) for i, s in enumerate(sides)]
+    vals = torch.from_numpy(np.concatenate([f.reshape(-1) for f in fields])).cuda()
+    b = dms.Batch(sides)
+    out = b.run(vals)
+    _check_fields(sides, fields, *out)
+
+
 def test_batch_graph_replay():
     fields = [_field(s, (i + 1) % 3, 200 + i) for i, s in enumerate(SIDES)]
     vals = torch.from_numpy(np.concatenate([f.reshape(-1) for f in fields])).cuda()
