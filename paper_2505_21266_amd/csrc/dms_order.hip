@@ -73,6 +73,16 @@ __device__ __forceinline__ int field_of(const int64_t *foff, int nfields, int64_
     return field_between(foff, 0, nfields - 1, i);
 }
 
+// Batches of up to kFieldPassFields fields sort 4-byte value keys and then,
+// in a last pass, by the field of each vertex id, found in an LDS copy of the
+// field offsets (fo, nfields + 1 entries).
+constexpr int kFieldPassFields = 256;
+
+__device__ __forceinline__ void load_field_offsets(int64_t *fo, const int64_t *foff, int nfields)
+{
+    for (int i = threadIdx.x; i <= nfields; i += blockDim.x) fo[i] = foff[i];
+}
+
 // Tile processed by this block.  Blocks are dealt round-robin to the 8 XCDs
 // (each with its own L2); giving each XCD a contiguous range of tiles lets
 // neighbouring tiles, whose digit runs share cache lines, merge in one L2.
@@ -154,12 +164,16 @@ __device__ __forceinline__ int64_t item_at(int64_t t0, int li, int last)
 // counts[d * ntiles + tile].
 // With ids != null (the last pass) it also histograms the vertex ids by
 // bucket (id >> bshift) into bcounts, for the grouped inversion.
-template <typename V, typename K, bool kFirst, int kThr>
+// kField (the last pass of a batch with 4-byte keys): the digit is the field
+// of the vertex id instead of a byte of the key.
+template <typename V, typename K, bool kFirst, int kThr, bool kField = false>
 __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, int shift,
                                                         uint32_t *counts, int64_t ntiles,
                                                         uint32_t *flags, const uint32_t *ids,
-                                                        int bshift, uint32_t *bcounts)
+                                                        int bshift, uint32_t *bcounts,
+                                                        const int64_t *foff, int nfields)
 {
+    __shared__ int64_t fo[kField ? kFieldPassFields + 1 : 1];
     constexpr int kW = kThr / kWave;
     __shared__ uint32_t hist[kW][kRadix];
     __shared__ uint32_t bhist[kW][kRadix];
@@ -182,6 +196,7 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
         (&hist[0][0])[i] = 0;
         (&bhist[0][0])[i] = 0;
     }
+    if constexpr (kField) load_field_offsets(fo, foff, nfields);
     __syncthreads();
     bool nan_any = false;
     if (ids) {
@@ -195,7 +210,9 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
         bool nan;
         const K key = to_key<V, K, kFirst>(raw[k], nan);
         nan_any |= valid && nan;
-        hist_add(hist[wave], (uint32_t)(key >> shift) & (kRadix - 1), valid);
+        uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
+        if constexpr (kField) d = (uint32_t)field_of(fo, nfields, bid[k]);
+        hist_add(hist[wave], d, valid);
     }
     __syncthreads();
     if (kFirst && __ballot(nan_any) && lane == 0) atomicOr(flags, (uint32_t)DMS_FLAG_NAN);
@@ -437,14 +454,15 @@ InvertPlan invert_plan(int64_t n)
 // Per-wave counts are 16-bit (at most a tile), so that the block's LDS stays
 // just under 40 KiB at 256 threads (four blocks per CU) and 75 KiB at 512
 // (two).
-template <typename K, int kThr>
+template <typename K, int kThr, bool kField = false>
 __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint32_t *src_ids,
                                                            int64_t n, int shift,
                                                            const uint32_t *offsets,
                                                            const uint32_t *boffsets, int64_t ntiles,
-                                                           const int64_t *foff, int bshift,
+                                                           const int64_t *foff, int nfields, int bshift,
                                                            uint32_t *pair_id, int32_t *pair_pos)
 {
+    __shared__ int64_t fo[kField ? kFieldPassFields + 1 : 1];
     constexpr int kW = kThr / kWave, kT = kThr * kItems;
     __shared__ uint16_t dwh[kW][kRadix];
     __shared__ uint16_t bwh[kW][kRadix];
@@ -459,6 +477,7 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
         (&bwh[0][0])[i] = 0;
     }
     zero_masks(S);
+    if constexpr (kField) load_field_offsets(fo, foff, nfields);
     __syncthreads();
 
     const int64_t tile = tile_of_block(ntiles);
@@ -469,7 +488,7 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
     // bucket rank inside the wave (each below 16 x 64 = 2^10) and its digit;
     // batches also keep the field
     uint32_t id[kItems], pk[kItems];
-    uint32_t fld[sizeof(K) == 8 ? kItems : 1];
+    uint32_t fld[sizeof(K) == 8 || kField ? kItems : 1];
     {
         K key[kItems];
 #pragma unroll
@@ -481,15 +500,18 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const bool valid = local_index(wave, k, lane) < count;
-            const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-            // the top byte (sign and exponent) takes few values: ballots match
-            // it faster than the LDS masks, which serve the random id buckets
+            uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+            if constexpr (kField) d = (uint32_t)field_of(fo, nfields, id[k]);
+            // the top byte (sign and exponent) takes few values, and a tile
+            // spans few fields: ballots match it faster than the LDS masks,
+            // which serve the random id buckets
             const uint32_t rd = wave_rank<false>(d, valid, dwh[wave], S.mk[wave]);
             const uint32_t rb = wave_rank<true>((id[k] >> bshift) & (kRadix - 1), valid, bwh[wave], S.mk[wave]);
             // settled here: otherwise the compiler sinks the rank popcounts past
             // the barrier and keeps every item's two 64-bit lane masks alive
             pk[k] = settled(rd | d << 10 | rb << 18);
-            if constexpr (sizeof(K) == 8) fld[k] = (uint32_t)(key[k] >> 32);
+            if constexpr (kField) fld[k] = d;
+            else if constexpr (sizeof(K) == 8) fld[k] = (uint32_t)(key[k] >> 32);
         }
     }
     __syncthreads();
@@ -511,7 +533,9 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
             const uint32_t b = (id[k] >> bshift) & (kRadix - 1);
             const int64_t g = (int64_t)gbase[d] + dwh[wave][d] + (pk[k] & 1023u);
             int64_t base = 0;
-            if constexpr (sizeof(K) == 8) {
+            if constexpr (kField) {
+                base = fo[fld[k]];
+            } else if constexpr (sizeof(K) == 8) {
                 if (foff) base = foff[fld[k]];
             }
             const uint32_t pos = bstart[b] + bwh[wave][b] + (pk[k] >> 18);
@@ -704,11 +728,14 @@ OrderLayout order_layout(int64_t n)
     return L;
 }
 
+// field_last: a batch of at most kFieldPassFields fields with 4-byte keys;
+// passes - 1 value passes, then the last pass orders by the field of each id.
 template <typename V, typename K>
 int run_order(const void *values, int64_t n, int passes, int32_t *order, char *ws, uint32_t *flags,
-              const int64_t *foff, int nfields, hipStream_t s)
+              const int64_t *foff, int nfields, hipStream_t s, bool field_last = false)
 {
     if (passes < 2) return DMS_E_ARG;
+    if (field_last && (sizeof(K) != 4 || !foff || nfields > kFieldPassFields)) return DMS_E_ARG;
     const OrderLayout L = order_layout<K>(n);
     const InvertPlan P = invert_plan(n);
     const int64_t ntiles = (n + kTile - 1) / kTile;
@@ -730,29 +757,37 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
         if (!last) {
             if (p == 0) {
                 hipLaunchKernelGGL((k_tile_hist<V, K, true, kWide>), wgrid, wblock, 0, s, src, n, shift,
-                                   counts, nwide, flags, nullptr, 0, nullptr);
+                                   counts, nwide, flags, nullptr, 0, nullptr, nullptr, 0);
                 exclusive_scan<uint32_t>(counts, nwide * kRadix, partials, s);
                 hipLaunchKernelGGL((k_scatter<V, K, true, kWide>), wgrid, wblock, 0, s, src, sids, n, shift,
                                    counts, nwide, keys[p & 1], ids[p & 1], foff, nfields);
             } else {
                 hipLaunchKernelGGL((k_tile_hist<V, K, false, kWide>), wgrid, wblock, 0, s, src, n, shift,
-                                   counts, nwide, flags, nullptr, 0, nullptr);
+                                   counts, nwide, flags, nullptr, 0, nullptr, nullptr, 0);
                 exclusive_scan<uint32_t>(counts, nwide * kRadix, partials, s);
                 hipLaunchKernelGGL((k_scatter<V, K, false, kWide>), wgrid, wblock, 0, s, src, sids, n,
                                    shift, counts, nwide, keys[p & 1], ids[p & 1], foff, nfields);
             }
             continue;
         }
-        hipLaunchKernelGGL((k_tile_hist<V, K, false, kWide>), wgrid, wblock, 0, s, src, n, shift, counts,
-                           nwide, flags, sids, P.bshift, bcounts);
+        if (field_last)
+            hipLaunchKernelGGL((k_tile_hist<V, K, false, kWide, true>), wgrid, wblock, 0, s, src, n, shift,
+                               counts, nwide, flags, sids, P.bshift, bcounts, foff, nfields);
+        else
+            hipLaunchKernelGGL((k_tile_hist<V, K, false, kWide>), wgrid, wblock, 0, s, src, n, shift, counts,
+                               nwide, flags, sids, P.bshift, bcounts, nullptr, 0);
         exclusive_scan<uint32_t>(counts, nwide * kRadix, partials, s);
         exclusive_scan<uint32_t>(bcounts, nwide * kRadix, bpartials, s);
         // level 0 into the free buffers; level 1 back into the last pass's
         // source buffers once they are read
         uint32_t *aid = (uint32_t *)keys[p & 1];
         int32_t *apos = (int32_t *)ids[p & 1];
-        hipLaunchKernelGGL((k_scatter_last<K, kWide>), wgrid, wblock, 0, s, (const K *)src, sids, n, shift,
-                           counts, bcounts, nwide, foff, P.bshift, aid, apos);
+        if (field_last)
+            hipLaunchKernelGGL((k_scatter_last<K, kWide, true>), wgrid, wblock, 0, s, (const K *)src, sids, n,
+                               shift, counts, bcounts, nwide, foff, nfields, P.bshift, aid, apos);
+        else
+            hipLaunchKernelGGL((k_scatter_last<K, kWide>), wgrid, wblock, 0, s, (const K *)src, sids, n, shift,
+                               counts, bcounts, nwide, foff, nfields, P.bshift, aid, apos);
         if (P.fine) {
             uint32_t *fid = (uint32_t *)keys[(p - 1) & 1];
             int32_t *fpos = (int32_t *)ids[(p - 1) & 1];
@@ -795,6 +830,8 @@ int launch_order_batch(const float *values, int64_t n, const int64_t *foff, int 
                        int32_t *order, char *ws, uint32_t *flags, hipStream_t s)
 {
     if (n == 0) return DMS_OK;
+    if (nfields <= kFieldPassFields)  // four value passes, then one field pass
+        return run_order<float, uint32_t>(values, n, 5, order, ws, flags, foff, nfields, s, true);
     return run_order<float, uint64_t>(values, n, batch_passes(nfields), order, ws, flags, foff, nfields, s);
 }
 
