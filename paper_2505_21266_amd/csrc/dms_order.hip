@@ -187,7 +187,8 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
     R raw[kItems];
     uint32_t bid[kItems];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) raw[k] = ((const R *)src)[item_at(t0, local_index(wave, k, lane), last)];
+    for (int k = 0; k < kItems; ++k)
+        if constexpr (!kField) raw[k] = ((const R *)src)[item_at(t0, local_index(wave, k, lane), last)];
     if (ids) {
 #pragma unroll
         for (int k = 0; k < kItems; ++k) bid[k] = ids[item_at(t0, local_index(wave, k, lane), last)];
@@ -207,11 +208,15 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const bool valid = local_index(wave, k, lane) < count;
-        bool nan;
-        const K key = to_key<V, K, kFirst>(raw[k], nan);
-        nan_any |= valid && nan;
-        uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
-        if constexpr (kField) d = (uint32_t)field_of(fo, nfields, bid[k]);
+        uint32_t d;
+        if constexpr (kField) {
+            d = (uint32_t)field_of(fo, nfields, bid[k]);
+        } else {
+            bool nan;
+            const K key = to_key<V, K, kFirst>(raw[k], nan);
+            nan_any |= valid && nan;
+            d = (uint32_t)(key >> shift) & (kRadix - 1);
+        }
         hist_add(hist[wave], d, valid);
     }
     __syncthreads();
@@ -494,14 +499,17 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const int64_t at = item_at(t0, local_index(wave, k, lane), count - 1);
-            key[k] = src[at];
+            if constexpr (!kField) key[k] = src[at];  // the field pass needs only the ids
             id[k] = src_ids[at];
         }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const bool valid = local_index(wave, k, lane) < count;
-            uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-            if constexpr (kField) d = (uint32_t)field_of(fo, nfields, id[k]);
+            uint32_t d;
+            if constexpr (kField)
+                d = (uint32_t)field_of(fo, nfields, id[k]);
+            else
+                d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
             // the top byte (sign and exponent) takes few values, and a tile
             // spans few fields: ballots match it faster than the LDS masks,
             // which serve the random id buckets
