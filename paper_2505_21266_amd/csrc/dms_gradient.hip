@@ -524,7 +524,43 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
     const bool full = x0 >= 0 && y0 >= 0 && z0 >= 0 && x0 + S::HX <= nx && y0 + S::HY <= ny &&
                       z0 + S::HZ <= nz;
     bool nan = false, nan_any = false;
-    if (full && nx * S::HY < (1ll << 31)) {
+    bool staged = false;  // uniform
+    if constexpr (GX == kWave) {
+      if (full) {
+        // inside the grid, rows of 66 orders: wave w loads rows w, w + 4, ...
+        // (64 consecutive orders from a row base computed in scalar
+        // registers, so the loads need no per-lane address arithmetic), and
+        // the first 2 x 54 threads load the rows' last two orders; every
+        // load is issued before any LDS store
+        constexpr int kRows = S::HY * S::HZ;
+        constexpr int kWavesB = kThreads / kWave;
+        constexpr int kPerRow = (kRows + kWavesB - 1) / kWavesB;
+        static_assert(S::HX == kWave + 2 && 2 * kRows <= kThreads, "row split");
+        const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+        const int64_t base0 = x0 + nx * (y0 + ny * z0), pstride = nx * ny;
+        typename Keys::H hv[kPerRow];
+#pragma unroll
+        for (int k = 0; k < kPerRow; ++k) {
+            const int r = min(wave + kWavesB * k, kRows - 1);
+            const int hz = r / S::HY, hy = r - hz * S::HY;
+            hv[k] = Keys::load(field, base0 + hz * pstride + hy * nx + lane, nan);
+            nan_any |= nan;
+        }
+        const int er = tid < 2 * kRows ? tid >> 1 : 0;
+        const int ez = er / S::HY, ey = er - ez * S::HY;
+        const typename Keys::H ev = Keys::load(field, base0 + ez * pstride + ey * nx + kWave + (tid & 1), nan);
+        nan_any |= nan;
+#pragma unroll
+        for (int k = 0; k < kPerRow; ++k) {
+            const int r = wave + kWavesB * k;
+            if (r < kRows) tile[r * S::HX + lane] = hv[k];
+        }
+        if (tid < 2 * kRows) tile[er * S::HX + kWave + (tid & 1)] = ev;
+        staged = true;
+      }
+    }
+    if (staged) {
+    } else if (full && nx * S::HY < (1ll << 31)) {
         // inside the grid: each thread issues a fixed number of loads (its
         // last one clamped into the halo) before any LDS store, so that all
         // are in flight at once; a 64-bit base per halo plane and a 32-bit
