@@ -404,7 +404,8 @@ __device__ __forceinline__ const uint4 *table_entry(uint32_t low, const C *o,
     if (npair == 7) return &g_regular[side * kPerm7 + code7];
     const uint32_t j = (uint32_t)__ffs(~one & 0x7fu) - 1u;
     const uint32_t side6 = (side & ((1u << j) - 1u)) | ((side >> (j + 1u)) << j);
-    if (eight) return defect8 + ((int64_t)(j * 64u + side6) * kPerm8 + code8);
+    static_assert(kDefect8 < (1ll << 32), "32-bit index into the wholly-lower table");
+    if (eight) return defect8 + ((j * 64u + side6) * (uint32_t)kPerm8 + code8);
     return &g_defect6[(j * 64u + side6) * kPerm7 + code7];
 }
 
@@ -602,10 +603,15 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
 
     // pass 1: table vertices; the others are listed
     const int64_t rbase = rec_off + (bx * GX) + w0 * ((by * GY) + w1 * bz);
+    // a 64-wide tile: vertex k of a thread lies in column lane and row
+    // wave + 4 k, the same row for the whole wave, so the row's part of the
+    // LDS and record addresses stays in scalar registers
+    const int wave_u = __builtin_amdgcn_readfirstlane(tid / kWave);
 #pragma unroll
     for (int k = 0; k < kTileVerts / kThreads; ++k) {
         const int v = tid + k * kThreads;
-        const int tx = v % GX, ty = v / GX;
+        const int tx = GX == kWave ? tid % kWave : v % GX;
+        const int ty = GX == kWave ? wave_u + (kThreads / kWave) * k : v / GX;
         if (bx * GX + tx < w0 && by * GY + ty < w1 && bz < w2) {
             const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
             C o[14], ox;
