@@ -607,22 +607,42 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
     // wave + 4 k, the same row for the whole wave, so the row's part of the
     // LDS and record addresses stays in scalar registers
     const int wave_u = __builtin_amdgcn_readfirstlane(tid / kWave);
+    // all of a thread's table reads are issued (a vertex with no entry reads
+    // a dummy one) before any record is stored, so that their latencies
+    // overlap instead of adding up
+    constexpr int kPer = kTileVerts / kThreads;
+    uint32_t gx[kPer], gy[kPer], gz[kPer], gw[kPer];  // the entries, as plain words
+    uint32_t state = 0;  // bit k: vertex k in the box; bit kPer + k: it has an entry
 #pragma unroll
-    for (int k = 0; k < kTileVerts / kThreads; ++k) {
+    for (int k = 0; k < kPer; ++k) {
         const int v = tid + k * kThreads;
         const int tx = GX == kWave ? tid % kWave : v % GX;
         const int ty = GX == kWave ? wave_u + (kThreads / kWave) * k : v / GX;
+        const uint4 *hit = nullptr;
         if (bx * GX + tx < w0 && by * GY + ty < w1 && bz < w2) {
             const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
             C o[14], ox;
             gather_orders<Keys, GX, GY>(tile, c, o, ox);
-            const uint32_t low = lower_mask(o, ox);
-            const uint4 *hit = table_entry(low, o, defect8);
-            if (hit)
-                rec[rbase + tx + w0 * ty] = *hit;
-            else
-                sh.list[atomicAdd(&sh.nlist, 1u)] = (uint16_t)v;
+            hit = table_entry(lower_mask(o, ox), o, defect8);
+            state |= 1u << k;
         }
+        if (hit) state |= 1u << (kPer + k);
+        const uint4 e = *(hit ? hit : g_regular);
+        gx[k] = e.x;
+        gy[k] = e.y;
+        gz[k] = e.z;
+        gw[k] = e.w;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (!((state >> k) & 1u)) continue;
+        const int v = tid + k * kThreads;
+        const int tx = GX == kWave ? tid % kWave : v % GX;
+        const int ty = GX == kWave ? wave_u + (kThreads / kWave) * k : v / GX;
+        if ((state >> (kPer + k)) & 1u)
+            rec[rbase + tx + w0 * ty] = make_uint4(gx[k], gy[k], gz[k], gw[k]);
+        else
+            sh.list[atomicAdd(&sh.nlist, 1u)] = (uint16_t)v;
     }
     __syncthreads();
     const uint32_t total = sh.nlist;
