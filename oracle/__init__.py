@@ -14,6 +14,7 @@ Functions:
   lower_stars(order, dims)   Robins' ProcessLowerStars over a box -> records
   lower_stars_sampled(...)   the same at sampled vertices, from the values
   pls_local(okey)            one lower star from 15 explicit keys
+  pls_batch(keys)            many lower stars from explicit keys
   decode_record(rec)         75 cell states of one record
   critical_simplices(...)    zero-persistence skip -> 4 code lists
   d0_pairs(...)              Algorithm 1 on the extremum graph
@@ -60,20 +61,21 @@ def _load():
     I64 = ctypes.c_int64
     I = ctypes.c_int
     lib.oracle_star_tables.argtypes = [P, P, P, P, P]
-    lib.oracle_order_f32.argtypes = [P, I64, P]
-    lib.oracle_order_f64.argtypes = [P, I64, P]
+    lib.oracle_order_f32.argtypes = [P, I64, P, I]
+    lib.oracle_order_f64.argtypes = [P, I64, P, I]
     lib.oracle_pls_local.argtypes = [P, I, P, P, P]
     lib.oracle_lower_stars.argtypes = [P, P, P, P, P, P, I, I, P]
     lib.oracle_lower_stars_sampled.argtypes = [P, I, P, P, I64, P, I, P]
     lib.oracle_decode_record.argtypes = [P, P]
-    lib.oracle_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P]
+    lib.oracle_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P, I]
+    lib.oracle_pls_batch.argtypes = [P, I64, P, I, P]
     lib.oracle_d0_pairs.argtypes = [P, P, P, P, I64, P, P, P]
     lib.oracle_filtration_sort.argtypes = [P, P, P, I64, I, P]
     lib.oracle_d2_pairs.argtypes = [P, P, P, P, I64, P, I64, P, P, P]
     for f in (lib.oracle_star_tables, lib.oracle_order_f32, lib.oracle_order_f64,
               lib.oracle_pls_local, lib.oracle_lower_stars, lib.oracle_lower_stars_sampled,
               lib.oracle_decode_record, lib.oracle_critical_simplices, lib.oracle_d0_pairs,
-              lib.oracle_filtration_sort, lib.oracle_d2_pairs):
+              lib.oracle_filtration_sort, lib.oracle_d2_pairs, lib.oracle_pls_batch):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -100,15 +102,16 @@ def star_tables():
     return dict(nb=nb, tri=tri, tet=tet, edge_tris=et, tri_tets=tt)
 
 
-def order(values):
-    """order[v] = position of v in the ascending (value, id) sort; int32, same shape."""
+def order(values, nthreads=1):
+    """order[v] = position of v in the ascending (value, id) sort; int32, same shape.
+    nthreads: threads of the sort (1 = one qsort; 0 = all, sorted runs merged)."""
     lib = _load()
     v = np.ascontiguousarray(values)
     out = np.empty(v.shape, np.int32)
     if v.dtype == np.float32:
-        rc = lib.oracle_order_f32(_p(v), v.size, _p(out))
+        rc = lib.oracle_order_f32(_p(v), v.size, _p(out), int(nthreads))
     elif v.dtype == np.float64:
-        rc = lib.oracle_order_f64(_p(v), v.size, _p(out))
+        rc = lib.oracle_order_f64(_p(v), v.size, _p(out), int(nthreads))
     else:
         raise TypeError("float32 or float64 expected")
     if rc == 1:
@@ -181,6 +184,20 @@ def pls_local(okey, literal=False):
     return st, rec, int(an[0])
 
 
+def pls_batch(keys, nthreads=0):
+    """Lower stars of many explicit neighbourhoods: keys is (m, 15) uint8 (x,
+    then neighbours 0..13; 255 = absent).  Returns rec (m, 4) uint32."""
+    lib = _load()
+    k = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 15)
+    rec = np.zeros((k.shape[0], 4), np.uint32)
+    an = np.zeros(1, np.int64)
+    if lib.oracle_pls_batch(_p(k), k.shape[0], _p(rec), int(nthreads), _p(an)) != 0:
+        raise RuntimeError("oracle pls_batch failed")
+    if an[0]:
+        raise RuntimeError("oracle anomaly count %d" % an[0])
+    return rec
+
+
 def decode_record(rec4):
     lib = _load()
     r = np.ascontiguousarray(np.asarray(rec4, dtype=np.uint32).reshape(4))
@@ -189,20 +206,21 @@ def decode_record(rec4):
     return st
 
 
-def critical_simplices(rec, dims, lo=None, hi=None, cap=None):
-    """Returns ([crit0, crit1, crit2, crit3] int64 code arrays, counts[4])."""
+def critical_simplices(rec, dims, lo=None, hi=None, cap=None, nthreads=1):
+    """Returns ([crit0, crit1, crit2, crit3] int64 code arrays, counts[4]).
+    nthreads: threads over the rows of the box (0 = all)."""
     lib = _load()
     dims, lo, hi = _box(dims, lo, hi)
     r = np.ascontiguousarray(rec, dtype=np.uint32)
     counts = np.zeros(4, np.int64)
     zero = np.zeros(4, np.int64)
     lib.oracle_critical_simplices(_p(r), _p(dims), _p(lo), _p(hi), None, None, None, None,
-                                  _p(zero), _p(counts))
+                                  _p(zero), _p(counts), int(nthreads))
     cap = counts.copy() if cap is None else _i64(cap)
     outs = [np.zeros(max(int(c), 1), np.int64) for c in cap]
     counts2 = np.zeros(4, np.int64)
     rc = lib.oracle_critical_simplices(_p(r), _p(dims), _p(lo), _p(hi), _p(outs[0]), _p(outs[1]),
-                                       _p(outs[2]), _p(outs[3]), _p(cap), _p(counts2))
+                                       _p(outs[2]), _p(outs[3]), _p(cap), _p(counts2), int(nthreads))
     if rc != 0:
         raise ValueError("bad box")
     return [outs[d][: min(int(counts2[d]), int(cap[d]))] for d in range(4)], counts2

@@ -161,15 +161,69 @@ static int cmp_vid(const void *pa, const void *pb)
     return (a->id < b->id) ? -1 : (a->id > b->id);
 }
 
-static int order_from_pairs(vid_t *p, int64_t n, int32_t *order)
+/* Number of threads a call uses: nthreads if positive, else every thread
+ * OpenMP offers. */
+static int threads_for(int nthreads)
 {
-    qsort(p, (size_t)n, sizeof(vid_t), cmp_vid);
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+/* Merges the sorted runs a[0, na) and b[0, nb) into out (a first on ties,
+ * so the merge is stable). */
+static void merge_runs(const vid_t *a, int64_t na, const vid_t *b, int64_t nb, vid_t *out)
+{
+    int64_t i = 0, j = 0, k = 0;
+    while (i < na && j < nb) out[k++] = cmp_vid(&b[j], &a[i]) < 0 ? b[j++] : a[i++];
+    while (i < na) out[k++] = a[i++];
+    while (j < nb) out[k++] = b[j++];
+}
+
+/* Sorts the pairs by (value, id): with several threads, one qsort per run
+ * of n / threads pairs, then rounds of pairwise merges of adjacent runs.
+ * Returns 0, or 2 if the merge buffer cannot be allocated. */
+static int sort_pairs(vid_t *p, int64_t n, int nthreads)
+{
+    int t = threads_for(nthreads);
+    if (t <= 1 || n < 4096) {
+        qsort(p, (size_t)n, sizeof(vid_t), cmp_vid);
+        return 0;
+    }
+    int64_t *b = (int64_t *)malloc(sizeof(int64_t) * (size_t)(t + 1));
+    vid_t *tmp = (vid_t *)malloc(sizeof(vid_t) * (size_t)n);
+    if (!b || !tmp) { free(b); free(tmp); return 2; }
+    for (int i = 0; i <= t; ++i) b[i] = n * i / t;
+#pragma omp parallel for num_threads(t) schedule(static, 1)
+    for (int i = 0; i < t; ++i) qsort(p + b[i], (size_t)(b[i + 1] - b[i]), sizeof(vid_t), cmp_vid);
+    vid_t *src = p, *dst = tmp;
+    for (int w = 1; w < t; w *= 2) {
+#pragma omp parallel for num_threads(t) schedule(dynamic, 1)
+        for (int i = 0; i < t; i += 2 * w) {
+            int m = i + w < t ? i + w : t, e = i + 2 * w < t ? i + 2 * w : t;
+            merge_runs(src + b[i], b[m] - b[i], src + b[m], b[e] - b[m], dst + b[i]);
+        }
+        vid_t *x = src; src = dst; dst = x;
+    }
+    if (src != p) memcpy(p, src, sizeof(vid_t) * (size_t)n);
+    free(b);
+    free(tmp);
+    return 0;
+}
+
+static int order_from_pairs(vid_t *p, int64_t n, int32_t *order, int nthreads)
+{
+    if (sort_pairs(p, n, nthreads)) return 2;
     for (int64_t r = 0; r < n; ++r) order[p[r].id] = (int32_t)r;
     return 0;
 }
 
-/* Returns 0 on success, 1 if a NaN was found, 2 on bad size / allocation. */
-int oracle_order_f32(const float *values, int64_t n, int32_t *order)
+/* nthreads: threads of the sort (0 = all).  Returns 0 on success, 1 if a
+ * NaN was found, 2 on bad size / allocation. */
+int oracle_order_f32(const float *values, int64_t n, int32_t *order, int nthreads)
 {
     if (n < 0 || n > 2147483647LL) return 2;
     vid_t *p = (vid_t *)malloc(sizeof(vid_t) * (size_t)(n > 0 ? n : 1));
@@ -180,12 +234,12 @@ int oracle_order_f32(const float *values, int64_t n, int32_t *order)
         p[i].v = (v == 0.0) ? 0.0 : v; /* -0.0 -> +0.0 */
         p[i].id = i;
     }
-    order_from_pairs(p, n, order);
+    int rc = order_from_pairs(p, n, order, nthreads);
     free(p);
-    return 0;
+    return rc;
 }
 
-int oracle_order_f64(const double *values, int64_t n, int32_t *order)
+int oracle_order_f64(const double *values, int64_t n, int32_t *order, int nthreads)
 {
     if (n < 0 || n > 2147483647LL) return 2;
     vid_t *p = (vid_t *)malloc(sizeof(vid_t) * (size_t)(n > 0 ? n : 1));
@@ -196,9 +250,9 @@ int oracle_order_f64(const double *values, int64_t n, int32_t *order)
         p[i].v = (v == 0.0) ? 0.0 : v;
         p[i].id = i;
     }
-    order_from_pairs(p, n, order);
+    int rc = order_from_pairs(p, n, order, nthreads);
     free(p);
-    return 0;
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -500,6 +554,29 @@ int oracle_pls_local(const int64_t *okey /*15*/, int literal, int8_t *states /*7
     return 0;
 }
 
+/*
+ * Many lower stars from explicit keys: keys holds m rows of 15 small keys
+ * (x, then neighbours 0..13; 255 = the neighbour is absent), rec receives 4
+ * words per row.  Each row is one pls_one call, as oracle_pls_local makes
+ * it; nthreads threads (0 = all) share the rows.  Returns 0, or -1.
+ */
+int oracle_pls_batch(const uint8_t *keys, int64_t m, uint32_t *rec, int nthreads,
+                     int64_t *anomalies)
+{
+    build_tables();
+    if (tables_built != 1 || m < 0) return -1;
+    int64_t an = 0;
+    int nt = threads_for(nthreads);
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1024) reduction(+ : an)
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t okey[15];
+        for (int u = 0; u < 15; ++u) okey[u] = keys[15 * r + u] == 255 ? -1 : (int64_t)keys[15 * r + u];
+        pls_one(okey, 0, &an, NULL, rec + 4 * r);
+    }
+    if (anomalies) *anomalies += an;
+    return 0;
+}
+
 static int box_ok(const int64_t *dims, const int64_t *lo, const int64_t *hi)
 {
     for (int c = 0; c < 3; ++c) {
@@ -538,13 +615,9 @@ int oracle_lower_stars(const int32_t *order, const int64_t *dims, const int64_t 
     if (tables_built != 1 || !box_ok(dims, lo, hi)) return -1;
     int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
     int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, an = 0;
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#else
-    (void)nthreads;
-#endif
+    int nt = threads_for(nthreads);
     int64_t rows = w1 * w2;
-#pragma omp parallel for schedule(dynamic, 4) reduction(+ : c0, c1, c2, c3, an)
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 4) reduction(+ : c0, c1, c2, c3, an)
     for (int64_t r = 0; r < rows; ++r) {
         int64_t j = lo[1] + r % w1, k = lo[2] + r / w1;
         for (int64_t i = lo[0]; i < hi[0]; ++i) {
@@ -584,12 +657,8 @@ int oracle_lower_stars_sampled(const void *values, int dtype, const int64_t *dim
     int64_t nx = dims[0], ny = dims[1], nz = dims[2], n = nx * ny * nz;
     int64_t an = 0;
     int nan_seen = 0, bad = 0;
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#else
-    (void)nthreads;
-#endif
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : an) reduction(| : nan_seen, bad)
+    int nt = threads_for(nthreads);
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 64) reduction(+ : an) reduction(| : nan_seen, bad)
     for (int64_t s = 0; s < m; ++s) {
         int64_t v = vids[s];
         if (v < 0 || v >= n) { bad = 1; continue; }
@@ -672,38 +741,64 @@ int oracle_decode_record(const uint32_t *rec, int8_t *states)
     return 0;
 }
 
+/* Visits the records of one row (j, k) of box [lo, hi): cnt[d] counts its
+ * critical cells of dimension d, and when crit is non-null each is written
+ * to crit[d][base[d] + its number in the row] if below cap[d]. */
+static void critical_row(const uint32_t *rec, const int64_t *dims, const int64_t *lo, const int64_t *hi,
+                         int64_t j, int64_t k, int64_t *const *crit, const int64_t *cap,
+                         const int64_t *base, int64_t *cnt)
+{
+    int64_t nx = dims[0], ny = dims[1];
+    int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1];
+    for (int d = 0; d < 4; ++d) cnt[d] = 0;
+    for (int64_t i = lo[0]; i < hi[0]; ++i) {
+        int64_t idx = (i - lo[0]) + w0 * ((j - lo[1]) + w1 * (k - lo[2]));
+        int64_t v = i + nx * (j + ny * k);
+        int8_t st[NCELL];
+        decode_record(rec + 4 * idx, st);
+        for (int c = 0; c < NCELL; ++c) {
+            if (st[c] != ST_CRIT) continue;
+            int d = c == 0 ? 0 : c < C_TRI(0) ? 1 : c < C_TET(0) ? 2 : 3;
+            int local = c == 0 ? 0 : c < C_TRI(0) ? c - C_EDGE(0)
+                                   : c < C_TET(0) ? c - C_TRI(0) : c - C_TET(0);
+            if (crit && crit[d] && base[d] + cnt[d] < cap[d]) crit[d][base[d] + cnt[d]] = (v << 8) | local;
+            ++cnt[d];
+        }
+    }
+}
+
 /*
- * Lists the critical cells of the records of box [lo, hi).  crit[d] (host
- * arrays, may be NULL) receive at most cap[d] codes; counts[d] always
- * receives the full count.  Returns 0, or -1 for bad arguments.
+ * Lists the critical cells of the records of box [lo, hi), in vertex-id
+ * order.  crit[d] (host arrays, may be NULL) receive at most cap[d] codes;
+ * counts[d] always receives the full count.  With several threads (nthreads,
+ * 0 = all) the rows of the box are counted first, their counts summed in row
+ * order into each row's first slot, and then every row writes its own
+ * slots.  Returns 0, -1 for bad arguments, -2 if memory runs out.
  */
 int oracle_critical_simplices(const uint32_t *rec, const int64_t *dims, const int64_t *lo,
                               const int64_t *hi, int64_t *crit0, int64_t *crit1, int64_t *crit2,
-                              int64_t *crit3, const int64_t *cap, int64_t *counts)
+                              int64_t *crit3, const int64_t *cap, int64_t *counts, int nthreads)
 {
     build_tables();
     if (tables_built != 1 || !box_ok(dims, lo, hi)) return -1;
     int64_t *crit[4] = {crit0, crit1, crit2, crit3};
-    int64_t cnt[4] = {0, 0, 0, 0};
-    int64_t nx = dims[0], ny = dims[1];
-    int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1];
-    for (int64_t k = lo[2]; k < hi[2]; ++k)
-        for (int64_t j = lo[1]; j < hi[1]; ++j)
-            for (int64_t i = lo[0]; i < hi[0]; ++i) {
-                int64_t idx = (i - lo[0]) + w0 * ((j - lo[1]) + w1 * (k - lo[2]));
-                int64_t v = i + nx * (j + ny * k);
-                int8_t st[NCELL];
-                decode_record(rec + 4 * idx, st);
-                for (int c = 0; c < NCELL; ++c) {
-                    if (st[c] != ST_CRIT) continue;
-                    int d = c == 0 ? 0 : c < C_TRI(0) ? 1 : c < C_TET(0) ? 2 : 3;
-                    int local = c == 0 ? 0 : c < C_TRI(0) ? c - C_EDGE(0)
-                                           : c < C_TET(0) ? c - C_TRI(0) : c - C_TET(0);
-                    if (crit[d] && cnt[d] < cap[d]) crit[d][cnt[d]] = (v << 8) | local;
-                    ++cnt[d];
-                }
-            }
-    for (int d = 0; d < 4; ++d) counts[d] = cnt[d];
+    int64_t w1 = hi[1] - lo[1], w2 = hi[2] - lo[2], rows = w1 * w2;
+    int64_t *rc = (int64_t *)malloc(sizeof(int64_t) * 4 * (size_t)(rows + 1));
+    if (!rc) return -2;
+    int nt = threads_for(nthreads);
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 16)
+    for (int64_t r = 0; r < rows; ++r)
+        critical_row(rec, dims, lo, hi, lo[1] + r % w1, lo[2] + r / w1, NULL, cap, NULL, rc + 4 * (r + 1));
+    for (int d = 0; d < 4; ++d) rc[d] = 0;
+    for (int64_t r = 1; r <= rows; ++r)
+        for (int d = 0; d < 4; ++d) rc[4 * r + d] += rc[4 * (r - 1) + d]; /* rc[4 r] = first slots of row r */
+    for (int d = 0; d < 4; ++d) counts[d] = rc[4 * rows + d];
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 16)
+    for (int64_t r = 0; r < rows; ++r) {
+        int64_t cnt[4];
+        critical_row(rec, dims, lo, hi, lo[1] + r % w1, lo[2] + r / w1, crit, cap, rc + 4 * r, cnt);
+    }
+    free(rc);
     return 0;
 }
 

@@ -275,3 +275,40 @@ def test_min_count_plain_definition():
                         break
                 mins += not low
     assert c[0] == mins
+
+
+@pytest.mark.parametrize("dims,lo,hi", [((40, 31, 22), None, None), ((34, 34, 9), (1, 1, 1), (33, 33, 8))])
+def test_threaded_extraction_equals_one_thread(dims, lo, hi):
+    """The row-parallel extraction lists exactly what the single-thread walk
+    over the box lists, in the same (vertex id, local index) order, and
+    respects the capacities."""
+    nx, ny, nz = dims
+    v = np.random.default_rng(7).random((nz, ny, nx)).astype(np.float32)
+    o = oracle.order(v)
+    rec, _, _ = oracle.lower_stars(o, dims, lo, hi)
+    one, c1 = oracle.critical_simplices(rec, dims, lo, hi, nthreads=1)
+    many, c8 = oracle.critical_simplices(rec, dims, lo, hi, nthreads=8)
+    assert (c1 == c8).all()
+    for d in range(4):
+        assert (one[d] == many[d]).all()
+        assert (np.diff(one[d]) > 0).all()
+    cap = [max(int(c) // 3, 1) for c in c1]
+    part, _ = oracle.critical_simplices(rec, dims, lo, hi, cap=cap, nthreads=8)
+    for d in range(4):
+        assert (part[d] == one[d][: cap[d]]).all()
+
+
+def test_pls_batch_equals_pls_local():
+    """The batched explicit-key call processes each row exactly as the
+    single-star call does (random keys, some neighbours absent)."""
+    rng = np.random.default_rng(11)
+    m = 400
+    keys = np.stack([rng.permutation(15) for _ in range(m)]).astype(np.uint8)
+    keys[rng.random((m, 15)) < 0.1] = 255
+    keys[:, 0] = np.where(keys[:, 0] == 255, 7, keys[:, 0])
+    got = oracle.pls_batch(keys, nthreads=4)
+    for r in range(m):
+        k = [(-1 if x == 255 else int(x)) for x in keys[r]]
+        _, want, an = oracle.pls_local(k)
+        assert an == 0
+        assert (got[r] == want).all(), r

@@ -49,3 +49,15 @@ def test_signed_zero_inf():
 def test_nan_rejected():
     with pytest.raises(ValueError):
         oracle.order(np.array([0.0, np.nan], np.float32))
+
+
+@pytest.mark.parametrize("n,threads", [(100000, 2), (100003, 3), (262144, 8), (5000, 16)])
+@pytest.mark.parametrize("kind", ["noise", "ties"])
+def test_threaded_sort_matches_stable_argsort(n, threads, kind):
+    """The oracle's threaded sort (sorted runs, then pairwise merges that take
+    the left run first on ties) gives numpy's stable argsort rank, ties by id
+    included, for run counts that are and are not powers of two."""
+    rng = np.random.default_rng(n + threads)
+    v = rng.random(n).astype(np.float32) if kind == "noise" else rng.integers(0, 9, n).astype(np.float64)
+    o = oracle.order(v, nthreads=threads)
+    assert (o == _stable_rank(v)).all()
