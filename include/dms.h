@@ -14,17 +14,19 @@
  *  - The processed ("owned") box is the half-open [lo, hi); vertices of the
  *    grid outside it are ghosts (Section 2.2): read, never processed.
  *  - Array arguments are DEVICE pointers owned by the caller unless marked
- *    [host].  Calls never allocate, free or synchronise; they enqueue work on
- *    `stream` (a hipStream_t, NULL = the default stream) and return.  One
- *    exception: the first dms_discrete_gradient (or dms_batch_create) on a
- *    device fills constant device tables of lower-star records -- 10 MB for
- *    the stars whose lower neighbours are one of each opposite pair, 36 MB
- *    and 289 MB (the latter allocated there, kept until the process ends)
- *    for those with one pair wholly upper or wholly lower -- and waits for
- *    them once.
+ *    [host].  The calls of the path (order, gradient, extraction, backward,
+ *    pairings' device halves) never allocate, free or synchronise; they
+ *    enqueue work on `stream` (a hipStream_t, NULL = the default stream) and
+ *    return.  Device set-up is explicit: dms_init, once per device, before
+ *    the first gradient call on it; dms_batch_create calls it itself.
  *  - Argument errors are returned synchronously as a dms_status and nothing
- *    is enqueued.  Data-dependent conditions found on the device are OR-ed
- *    into *dev_flags (a device uint32 the caller zeroes), read after a sync.
+ *    is enqueued; argument checks come before any device query, so they need
+ *    no GPU.  A call that would launch work returns DMS_E_UNSUPPORTED when
+ *    the current device is not a gfx950 (or there is no device), and the
+ *    gradient calls return DMS_E_NOT_INITIALISED before dms_init succeeded
+ *    on the current device.  Data-dependent conditions found on the device
+ *    are OR-ed into *dev_flags (a device uint32 the caller zeroes), read
+ *    after a sync.
  *  - Workspaces are caller-owned device buffers of at least the size the
  *    matching *_workspace_size call returns; their contents on entry are
  *    ignored.
@@ -44,8 +46,9 @@ typedef enum {
     DMS_E_ARG = 1,         /* null pointer, dims < 1, box outside the grid, bad dtype */
     DMS_E_SIZE = 2,        /* n > 2^31 - 1 vertices: int32 orders cannot rank them */
     DMS_E_WORKSPACE = 3,   /* workspace pointer null or smaller than required */
-    DMS_E_UNSUPPORTED = 4, /* no gfx950 device current */
-    DMS_E_HIP = 5          /* a HIP runtime call (launch) failed */
+    DMS_E_UNSUPPORTED = 4, /* the current device is not a gfx950, or there is no device */
+    DMS_E_HIP = 5,         /* a HIP runtime call (launch) failed */
+    DMS_E_NOT_INITIALISED = 6 /* a gradient call before dms_init on the current device */
 } dms_status;
 
 /* bits OR-ed into *dev_flags by the device */
@@ -63,6 +66,19 @@ const char *dms_status_str(int status);
 
 /* Library version string (static). */
 const char *dms_version(void);
+
+/*
+ * Device set-up for the current device -- the tabulated lower stars of
+ * Section 2.3: a vertex whose lower neighbours are one member of each
+ * opposite neighbour pair, or one of each but for a single pair with no or
+ * both members lower, has its record looked up instead of running Robins'
+ * pairing; the tables are filled once, by the same pairing code, on
+ * `stream`.  Checks that the current device is a gfx950 (else
+ * DMS_E_UNSUPPORTED), allocates the tables (held until the process ends),
+ * fills them and synchronises `stream` once.  Idempotent per device and
+ * safe to call from several threads.  Errors: DMS_E_UNSUPPORTED, DMS_E_HIP.
+ */
+int dms_init(void *stream);
 
 /*
  * Copies the library's compile-time Kuhn star tables to [host] arrays:
@@ -166,23 +182,37 @@ int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3], const int
                            size_t workspace_bytes, uint32_t *dev_flags, void *stream);
 
 /* ----------------------------------------------------------------------------
- * Backward of the D0 birth/death values -- Section 2.5: a pair is embedded
- * at (f(birth simplex), f(death simplex)) where f of a simplex is its
- * highest vertex value, so d(birth)/d(f) and d(death)/d(f) are indicator
- * vectors at the max vertex of each simplex.
+ * Values of simplices -- Section 2.5: a persistence pair is embedded at
+ * (f(birth simplex), f(death simplex)), where f of a simplex is the value of
+ * its highest vertex.  out[i] = values[codes[i] >> 8] as float64 (codes as
+ * dms_critical_simplices writes them; values DMS_F32 or DMS_F64, n
+ * entries).  A code naming a vertex outside [0, n) gives NaN.
+ * Errors: DMS_E_ARG (bad dtype, null pointer with count > 0), DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+int dms_simplex_values(const void *values, int dtype, int64_t n, const int64_t *codes, int64_t count,
+                       double *out, void *stream);
+
+/* ----------------------------------------------------------------------------
+ * Backward of the birth/death values (D0 or D2 pairs) -- Section 2.5: f of a
+ * simplex is its highest vertex value, so d(birth)/d(f) and d(death)/d(f)
+ * are indicator vectors at the max vertex of each simplex.
  *
  * grad[v] = sum over pairs p with maxv(birth_code[p]) == v of g_birth[p]
  *         + sum over pairs p with maxv(death_code[p]) == v of g_death[p],
- * where maxv(code) = code >> 8.  grad (n float64) is overwritten.  Summation
- * is deterministic: the pairs are processed so that each vertex receives its
- * contributions in pair order when the codes of equal max vertex are
- * adjacent (e.g. pairs listed by death code); otherwise atomic adds keep it
- * correct up to rounding order.  Codes naming vertices outside [0, n) are ignored.
- * Errors: DMS_E_ARG (null pointer with npairs > 0 or n > 0), DMS_E_HIP.
+ * where maxv(code) = code >> 8.  grad (n float64) is overwritten.  The sum
+ * is deterministic: each vertex adds its contributions in one fixed order
+ * (the births in pair order, then the deaths in pair order), after a stable
+ * sort of the 2 * npairs contributions by vertex; no atomics.  Codes naming
+ * vertices outside [0, n) are ignored.
+ * workspace: dms_gradient_backward_workspace_size(npairs) bytes.
+ * Errors: DMS_E_ARG (null pointer with npairs > 0 or n > 0, npairs over
+ * 2^30), DMS_E_WORKSPACE, DMS_E_UNSUPPORTED, DMS_E_HIP.
  * -------------------------------------------------------------------------- */
+size_t dms_gradient_backward_workspace_size(int64_t npairs);
 int dms_gradient_backward(const int64_t *birth_code, const int64_t *death_code,
                           const double *g_birth, const double *g_death, int64_t npairs,
-                          double *grad, int64_t n, void *stream);
+                          double *grad, int64_t n, void *workspace, size_t workspace_bytes,
+                          void *stream);
 
 /* ----------------------------------------------------------------------------
  * D0 pairing on the host -- Section 2.6 and Algorithm 1 (PairExtremaSaddles).

@@ -19,14 +19,15 @@ LIB_PATH = os.path.join(_HERE, "libdms.so")
 DMS_F32, DMS_F64 = 0, 1
 FLAG_NAN, FLAG_CAPACITY, FLAG_BADCODE = 1, 2, 4
 STATUS = {0: "DMS_OK", 1: "DMS_E_ARG", 2: "DMS_E_SIZE", 3: "DMS_E_WORKSPACE",
-          4: "DMS_E_UNSUPPORTED", 5: "DMS_E_HIP"}
+          4: "DMS_E_UNSUPPORTED", 5: "DMS_E_HIP", 6: "DMS_E_NOT_INITIALISED"}
 
 # every symbol include/dms.h declares
-SYMBOLS = ("dms_status_str", "dms_version", "dms_star_tables", "dms_order_workspace_size",
+SYMBOLS = ("dms_status_str", "dms_version", "dms_init", "dms_star_tables", "dms_order_workspace_size",
            "dms_order", "dms_gradient_workspace_size", "dms_discrete_gradient",
            "dms_discrete_gradient_values",
            "dms_critical_workspace_size",
-           "dms_critical_simplices", "dms_gradient_backward", "dms_d0_pairs_host",
+           "dms_critical_simplices", "dms_simplex_values", "dms_gradient_backward_workspace_size",
+           "dms_gradient_backward", "dms_d0_pairs_host",
            "dms_batch_create", "dms_batch_workspace_size", "dms_batch_total", "dms_batch_variant",
            "dms_batch_run", "dms_batch_destroy", "dms_d0_workspace_size", "dms_d0_triplets",
            "dms_d0_pairs_sorted_host", "dms_critical_sort_workspace_size", "dms_critical_sort",
@@ -55,6 +56,7 @@ def lib():
     L.dms_status_str.restype = ctypes.c_char_p
     L.dms_version.argtypes = []
     L.dms_version.restype = ctypes.c_char_p
+    L.dms_init.argtypes = [P]
     L.dms_star_tables.argtypes = [P, P, P, P, P]
     L.dms_order_workspace_size.argtypes = [I64, I]
     L.dms_order_workspace_size.restype = SZ
@@ -66,7 +68,10 @@ def lib():
     L.dms_critical_workspace_size.argtypes = [P, P, P]
     L.dms_critical_workspace_size.restype = SZ
     L.dms_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
-    L.dms_gradient_backward.argtypes = [P, P, P, P, I64, P, I64, P]
+    L.dms_simplex_values.argtypes = [P, I, I64, P, I64, P, P]
+    L.dms_gradient_backward_workspace_size.argtypes = [I64]
+    L.dms_gradient_backward_workspace_size.restype = SZ
+    L.dms_gradient_backward.argtypes = [P, P, P, P, I64, P, I64, P, SZ, P]
     L.dms_d0_pairs_host.argtypes = [P, P, P, P, I64, P, P, I64, P]
     L.dms_batch_create.argtypes = [P, I, I, I, ctypes.c_char_p, P]
     L.dms_batch_workspace_size.argtypes = [P]
@@ -88,7 +93,7 @@ def lib():
     L.dms_d2_workspace_size.restype = SZ
     L.dms_d2_triplets.argtypes = [P, P, P, P, I64, P, I64, P, P, P, P, P, P, SZ, P, P]
     L.dms_d2_pairs_sorted_host.argtypes = [P, P, P, I64, P, I64, P, P, I64, P]
-    for f in ("dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_discrete_gradient_values",
+    for f in ("dms_init", "dms_simplex_values", "dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_discrete_gradient_values",
               "dms_critical_simplices", "dms_d0_triplets", "dms_d0_pairs_sorted_host", "dms_critical_sort",
               "dms_d2_triplets", "dms_d2_pairs_sorted_host",
               "dms_gradient_backward", "dms_d0_pairs_host", "dms_batch_create", "dms_batch_variant",
@@ -101,6 +106,23 @@ def lib():
 def _check(status, where):
     if status != 0:
         raise DmsError(status, where)
+
+
+_ready = set()
+
+
+def init(device=None):
+    """dms_init on a device (once per device and process): checks that it is a
+    gfx950 and fills the library's lower-star tables, synchronising torch's
+    current stream of that device once."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if idx in _ready:
+        return
+    with torch.cuda.device(idx):
+        _check(lib().dms_init(ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream)), "dms_init")
+    _ready.add(idx)
 
 
 def _arr3(v):
@@ -248,6 +270,7 @@ def discrete_gradient(order_t, lo=None, hi=None, out=None, queue=True, workspace
     d, dp = _arr3(dims)
     l, lp = _arr3(lo)
     h, hp = _arr3(hi)
+    init(order_t.device)
     ws, wbytes = None, 0
     if queue and nbox > 0:
         wbytes = int(lib().dms_gradient_workspace_size(dp, lp, hp))
@@ -284,6 +307,7 @@ def discrete_gradient_values(values, lo=None, hi=None, out=None, queue=True, wor
     own_flags = flags is None
     if own_flags:
         flags = new_flags(values.device)
+    init(values.device)
     ws, wbytes = None, 0
     if queue and nbox > 0:
         wbytes = int(lib().dms_gradient_workspace_size(dp, lp, hp))
@@ -343,8 +367,24 @@ def critical_simplices(rec, dims, lo=None, hi=None, cap=None, flags=None, counts
     return lists, counts
 
 
+def simplex_values(values, codes, out=None):
+    """f of each simplex, the value of its highest vertex (dms_simplex_values):
+    float64 tensor of codes' length."""
+    import torch
+    _require_gpu(values, "values")
+    _require_gpu(codes, "codes")
+    if codes.dtype != torch.int64:
+        raise TypeError("codes must be int64")
+    if out is None:
+        out = torch.empty(codes.numel(), dtype=torch.float64, device=codes.device)
+    _check(lib().dms_simplex_values(_ptr(values), _dtype_code(values), values.numel(), _ptr(codes),
+                                    codes.numel(), _ptr(out), _stream(codes)), "dms_simplex_values")
+    return out
+
+
 def gradient_backward(birth_code, death_code, g_birth, g_death, n, out=None):
-    """dL/df from dL/d(birth, death) of D0 pairs (dms_gradient_backward)."""
+    """dL/df from dL/d(birth, death) of persistence pairs (dms_gradient_backward):
+    each vertex sums its contributions in one fixed order (deterministic)."""
     import torch
     for t, nm in ((birth_code, "birth_code"), (death_code, "death_code"), (g_birth, "g_birth"),
                   (g_death, "g_death")):
@@ -352,8 +392,11 @@ def gradient_backward(birth_code, death_code, g_birth, g_death, n, out=None):
     np_ = birth_code.numel()
     if out is None:
         out = torch.empty(int(n), dtype=torch.float64, device=birth_code.device)
+    wbytes = int(lib().dms_gradient_backward_workspace_size(np_))
+    ws = torch.empty(max(wbytes, 256), dtype=torch.uint8, device=birth_code.device)
     _check(lib().dms_gradient_backward(_ptr(birth_code), _ptr(death_code), _ptr(g_birth),
-                                       _ptr(g_death), np_, _ptr(out), int(n), _stream(out)),
+                                       _ptr(g_death), np_, _ptr(out), int(n), _ptr(ws), ws.numel(),
+                                       _stream(out)),
            "dms_gradient_backward")
     return out
 

@@ -4,8 +4,8 @@ Forward (Section 2.5, 2.6): GPU order, discrete gradient and critical
 simplices; the extremum graph on the GPU (D0: descents from the critical
 edges, triplets sorted by edge; D2: ascents on the dual complex from the
 critical triangles, triplets by decreasing triangle), the union-find on the
-host over the sorted triplets; births and deaths are gathered from the field
-as the highest vertex value of each simplex.  Backward: the library's
+host over the sorted triplets; births and deaths are the highest vertex
+values of each simplex (dms_simplex_values).  Backward: the library's
 scatter kernel sends dL/d(birth, death) to the max vertices.
 """
 import numpy as np
@@ -18,7 +18,8 @@ def _torch():
 
 def _make():
     torch = _torch()
-    from . import critical_simplices, d0_pairs, d2_pairs, discrete_gradient, dims_of, gradient_backward, order
+    from . import (critical_simplices, d0_pairs, d2_pairs, dims_of, discrete_gradient, gradient_backward,
+                   order, simplex_values)
 
     def _backward(ctx, g_births, g_deaths):
         birth_code, death_code = ctx.saved_tensors
@@ -30,11 +31,10 @@ def _make():
         return grad.reshape(ctx.shape)
 
     def _finish(ctx, field, birth_code, death_code):
-        flat = field.reshape(-1)
-        births = flat[birth_code >> 8]
-        deaths = flat[death_code >> 8]
+        births = simplex_values(field, birth_code).to(field.dtype)
+        deaths = simplex_values(field, death_code).to(field.dtype)
         ctx.save_for_backward(birth_code, death_code)
-        ctx.n = flat.numel()
+        ctx.n = field.numel()
         ctx.shape = field.shape
         return births, deaths
 

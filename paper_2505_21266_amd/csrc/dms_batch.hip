@@ -176,6 +176,10 @@ extern "C" int dms_batch_create(const int64_t *dims, int nfields, int dtype, int
         delete b;
         return DMS_E_SIZE;
     }
+    if (const int dc = dms::device_check()) {
+        delete b;
+        return dc;
+    }
     b->signature = fnv1a(dims, 3 * (size_t)nfields);
     std::vector<int64_t> ts(nfields + 1);
     bool ok = hipMalloc(&b->d_fields, sizeof(dms::BatchField) * nfields) == hipSuccess &&
@@ -199,7 +203,7 @@ extern "C" int dms_batch_create(const int64_t *dims, int nfields, int dtype, int
              hipMemcpy(b->d_tile_field[v], tf.data(), sizeof(uint16_t) * tf.size(), hipMemcpyHostToDevice) == hipSuccess;
     }
     ok = ok && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess &&
-         dms::ensure_regular_table(b->cap_stream) == DMS_OK;
+         dms::init_tables(b->cap_stream) == DMS_OK;
     if (!ok) {
         dms_batch_destroy(b);
         return DMS_E_HIP;
@@ -237,6 +241,7 @@ extern "C" int dms_batch_run(dms_batch *b, const void *values, int32_t *order, u
     for (int d = 0; d < 4; ++d)
         if (cap[d] < 0 || (cap[d] > 0 && !crit[d])) return DMS_E_ARG;
     if (!ws || ws_bytes < dms_batch_workspace_size(b)) return DMS_E_WORKSPACE;
+    if (const int dc = dms::device_check()) return dc;
     hipStream_t s = (hipStream_t)stream;
     if (!b->tuned) {
         // tuning pass, outside the graph: order once, then time every tile shape

@@ -46,6 +46,10 @@ inline bool grid_size_values_ok(const int64_t *dims)
     return dims[2] <= (1LL << 40) / plane;
 }
 
+// DMS_OK when the current device is a gfx950 (its properties are read once
+// per device and remembered), else DMS_E_UNSUPPORTED (also without a device).
+int device_check();
+
 inline int launch_status()
 {
     hipError_t e = hipGetLastError();

@@ -638,6 +638,7 @@ extern "C" int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3]
     if (nbox > 0 && !rec) return DMS_E_ARG;
     const size_t need = dms_critical_workspace_size(dims, lo, hi);
     if (!workspace || workspace_bytes < need) return DMS_E_WORKSPACE;
+    if (const int dc = device_check()) return dc;
     hipStream_t s = (hipStream_t)stream;
     const int64_t ntiles = (nbox + kTileRecs - 1) / kTileRecs;
     const int64_t len = 4 * ntiles + 1;

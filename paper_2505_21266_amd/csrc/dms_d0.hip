@@ -175,6 +175,7 @@ extern "C" int dms_d0_triplets(const uint32_t *rec, const int32_t *order, const 
     const int64_t n = dims[0] * dims[1] * dims[2];
     const D0Layout L = d0_layout(n, n1);
     if (!workspace || workspace_bytes < L.total) return DMS_E_WORKSPACE;
+    if (const int dc = device_check()) return dc;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
     int32_t *next = (int32_t *)(ws + L.next), *root = (int32_t *)(ws + L.root);

@@ -286,6 +286,7 @@ extern "C" int dms_d2_triplets(const uint32_t *rec, const int32_t *order, const 
         return DMS_E_ARG;
     const D2Layout L = d2_layout(n2, n3);
     if (!workspace || workspace_bytes < L.total) return DMS_E_WORKSPACE;
+    if (const int dc = device_check()) return dc;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
     int32_t *m0 = (int32_t *)(ws + L.m0), *m1 = (int32_t *)(ws + L.m1), *rank = (int32_t *)(ws + L.rank);

@@ -210,6 +210,7 @@ extern "C" int dms_critical_sort(const int64_t *codes, int64_t count, int dim, c
     if (count == 0) return DMS_OK;
     if (!codes || !order || !sorted || !dev_flags || sorted == codes) return DMS_E_ARG;
     if (!workspace || workspace_bytes < dms_critical_sort_workspace_size(count)) return DMS_E_WORKSPACE;
+    if (const int dc = device_check()) return dc;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
     int32_t *rank = (int32_t *)ws;

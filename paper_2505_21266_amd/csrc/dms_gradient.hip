@@ -920,8 +920,9 @@ std::mutex g_table_mutex;
 uint4 *g_defect8_ptr[64];  // per device, held until the process ends
 }
 
-int ensure_regular_table(hipStream_t s)
+int init_tables(hipStream_t s)
 {
+    if (const int dc = device_check()) return dc;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DMS_E_HIP;
     const uint64_t bit = 1ull << dev;
@@ -945,12 +946,20 @@ int ensure_regular_table(hipStream_t s)
     return DMS_OK;
 }
 
-// The current device's |L| = 8 table (null before ensure_regular_table).
+// The current device's |L| = 8 table (null before init_tables).
 static const uint4 *defect8_table()
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
     return (g_regular_ready.load() >> dev) & 1u ? g_defect8_ptr[dev] : nullptr;
+}
+
+// DMS_OK when the current device is a gfx950 whose tables init_tables has
+// filled; DMS_E_UNSUPPORTED or DMS_E_NOT_INITIALISED otherwise.
+int tables_ready()
+{
+    if (const int dc = device_check()) return dc;
+    return defect8_table() ? DMS_OK : DMS_E_NOT_INITIALISED;
 }
 
 
@@ -1068,8 +1077,7 @@ extern "C" int dms_discrete_gradient(const int32_t *order, const int64_t dims[3]
     if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
     if (!order || !rec) return DMS_E_ARG;
     if (workspace && workspace_bytes < gradient_workspace_size(w0 * w1 * w2)) return DMS_E_WORKSPACE;
-    const int st = ensure_regular_table((hipStream_t)stream);
-    if (st) return st;
+    if (const int st = tables_ready()) return st;
     return launch_gradient(0, order, dims, lo, hi, rec, (char *)workspace, (hipStream_t)stream);
 }
 
@@ -1086,11 +1094,12 @@ extern "C" int dms_discrete_gradient_values(const void *values, int dtype, const
     if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
     if (!values || !rec || !dev_flags) return DMS_E_ARG;
     if (workspace && workspace_bytes < gradient_workspace_size(w0 * w1 * w2)) return DMS_E_WORKSPACE;
-    const int st = ensure_regular_table((hipStream_t)stream);
-    if (st) return st;
+    if (const int st = tables_ready()) return st;
     if (dtype == DMS_F32)
         return launch_gradient_keys<F32Keys>(0, values, dims, lo, hi, rec, (char *)workspace, dev_flags,
                                              (hipStream_t)stream);
     return launch_gradient_keys<F64Keys>(0, values, dims, lo, hi, rec, (char *)workspace, dev_flags,
                                          (hipStream_t)stream);
 }
+
+extern "C" int dms_init(void *stream) { return dms::init_tables((hipStream_t)stream); }

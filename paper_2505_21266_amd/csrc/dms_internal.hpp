@@ -20,8 +20,9 @@ constexpr int kTileVertsPerBlock = 1024;
 constexpr int kGradVariants = 3;
 constexpr int kTileX[kGradVariants] = {64, 32, 16};
 
-// Fills the device's regular-vertex table on first use (one synchronisation).
-int ensure_regular_table(hipStream_t s);
+// Checks the device and fills its lower-star tables once (one
+// synchronisation of s); later calls return at once.
+int init_tables(hipStream_t s);
 // ws: gradient_workspace_size(owned vertices) bytes for the queue of
 // general vertices, or null (every tile then pairs its own).
 size_t gradient_workspace_size(int64_t owned);

@@ -861,6 +861,7 @@ extern "C" int dms_order(const void *values, int dtype, int64_t n, int32_t *orde
     if (n == 0) return DMS_OK;
     if (!values || !order || !dev_flags) return DMS_E_ARG;
     if (!workspace || workspace_bytes < dms_order_workspace_size(n, dtype)) return DMS_E_WORKSPACE;
+    if (const int dc = dms::device_check()) return dc;
     hipStream_t s = (hipStream_t)stream;
     if (dtype == DMS_F32)
         return dms::run_order<float, uint32_t>(values, n, 4, order, (char *)workspace, dev_flags,

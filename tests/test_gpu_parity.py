@@ -626,6 +626,45 @@ def test_d2_backward_config5():
     assert np.abs(want).max() > 0
 
 
+def test_backward_fixed_summation_order():
+    """Contributions to one vertex from births and deaths of pairs listed in
+    any order are summed in one fixed order -- the births by pair index,
+    then the deaths by pair index -- with values for which another order
+    gives another double; vertices named by no pair get zero, codes outside
+    the grid are dropped."""
+    bv = np.array([3, 9, 7, 1, 4, 7, 55], np.int64)   # vertex 55 is outside n = 40
+    dv = np.array([7, 2, 7, 7, 9, 6, 3], np.int64)
+    gb = np.array([0.5, 2.0, 1e16, -3.0, 0.25, 1.0, 8.0])
+    gd = np.array([-1e16, 4.0, 1.0, 1.0, 1e-3, -2.0, 0.125])
+    want = np.zeros(40)
+    for v in range(40):
+        acc = 0.0
+        for p in range(bv.size):
+            if bv[p] == v:
+                acc += gb[p]
+        for p in range(dv.size):
+            if dv[p] == v:
+                acc += gd[p]
+        want[v] = acc
+    assert want[7] == 2.0  # ((1e16 + 1) - 1e16) + 1 + 1 in this order; other orders differ
+    got = dms.gradient_backward(_dev(bv << 8), _dev((dv << 8) | 5), _dev(gb), _dev(gd), 40).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+def test_d2_backward_deterministic():
+    """Two runs of the D2 form on the 128^3 float64 workload give bitwise
+    equal gradients (triangles and tets can share a max vertex, out of pair
+    order)."""
+    f = inputs.config5()
+    grads = []
+    for _ in range(2):
+        x = _dev(f).requires_grad_(True)
+        births, deaths = dms.PersistenceD2.apply(x)
+        ((deaths - births) ** 2).sum().backward()
+        grads.append(x.grad.cpu().numpy().copy())
+    assert np.array_equal(grads[0].view(np.uint64), grads[1].view(np.uint64))
+
+
 def test_backward_kernel_runs():
     # several deaths on one vertex, given adjacent: summed in pair order
     bc = _dev(np.array([5 << 8, 9 << 8, 11 << 8], np.int64))

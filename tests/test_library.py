@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_status_strings(L):
-    for s in range(6):
+    for s in range(7):
         assert L.dms_status_str(s).decode().startswith("DMS_")
     assert b"gfx950" in L.dms_version()
 
@@ -108,9 +108,47 @@ def test_argument_errors(L):
                                     1 << 20, fake, None) == 1
     assert L.dms_critical_workspace_size(dp, lp, badp) == 0
     # backward
-    assert L.dms_gradient_backward(None, fake, fake, fake, 3, fake, 10, None) == 1
-    assert L.dms_gradient_backward(fake, fake, fake, fake, 3, None, 10, None) == 1
-    assert L.dms_gradient_backward(fake, fake, fake, fake, -1, fake, 10, None) == 1
+    need = L.dms_gradient_backward_workspace_size(3)
+    assert need >= 6 * 16
+    assert L.dms_gradient_backward(None, fake, fake, fake, 3, fake, 10, fake, need, None) == 1
+    assert L.dms_gradient_backward(fake, fake, fake, fake, 3, None, 10, fake, need, None) == 1
+    assert L.dms_gradient_backward(fake, fake, fake, fake, -1, fake, 10, fake, need, None) == 1
+    assert L.dms_gradient_backward(fake, fake, fake, fake, (1 << 30) + 1, fake, 10, fake, need, None) == 1
+    assert L.dms_gradient_backward(fake, fake, fake, fake, 3, fake, 10, fake, need - 1, None) == 3
+    assert L.dms_gradient_backward(fake, fake, fake, fake, 3, fake, 10, None, 0, None) == 3
+    assert L.dms_gradient_backward(fake, fake, fake, fake, 3, fake, 0, None, 0, None) == 0  # nothing to write
+    # simplex values
+    assert L.dms_simplex_values(fake, 2, 10, fake, 3, fake, None) == 1
+    assert L.dms_simplex_values(None, 0, 10, fake, 3, fake, None) == 1
+    assert L.dms_simplex_values(fake, 0, 10, fake, -1, fake, None) == 1
+    assert L.dms_simplex_values(None, 0, 10, None, 0, None, None) == 0
+
+
+def test_no_device_is_unsupported(L):
+    """Without a gfx950 device (this host has none), calls whose arguments
+    are valid return DMS_E_UNSUPPORTED instead of launching: dms_init, the
+    gradient (which also needs dms_init), the order and the extraction."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    P = ctypes.c_void_p
+    fake = P(4096)  # never dereferenced: the device check fails first
+    d, dp = _a3([4, 4, 4])
+    l, lp = _a3([0, 0, 0])
+    h, hp = _a3([4, 4, 4])
+    assert L.dms_init(None) == 4
+    assert L.dms_discrete_gradient(fake, dp, lp, hp, fake, None, 0, None) == 4
+    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, None, 0, fake, None) == 4
+    assert L.dms_order(fake, 0, 64, fake, fake, 1 << 30, fake, None) == 4
+    cap, capp = _a3([0, 0, 0, 0])
+    assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, capp, fake, fake, 1 << 20,
+                                    fake, None) == 4
+    need = L.dms_gradient_backward_workspace_size(3)
+    assert L.dms_gradient_backward(fake, fake, fake, fake, 3, fake, 10, fake, need, None) == 4
+    assert L.dms_simplex_values(fake, 0, 10, fake, 3, fake, None) == 4
+    out = P()
+    assert L.dms_batch_create(d.ctypes.data_as(P), 1, 0, 0, None, ctypes.byref(out)) == 4
+    assert not out.value
 
 
 @pytest.mark.parametrize("dims,seed", [((8, 8, 8), 1), ((13, 9, 11), 2), ((32, 32, 32), 3)])
