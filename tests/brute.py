@@ -240,3 +240,54 @@ def critical_by_dim(critset):
     for s in critset:
         out[len(s) - 1] += 1
     return out
+
+
+def hand_star_grid(rank_of_neighbour, upper_ranks, tables):
+    """A 3x3x3 grid order whose centre x = vertex 13 has neighbour e at rank
+    rank_of_neighbour[e] among x's neighbours: ranks in upper_ranks lie above
+    x, the others below; the 12 vertices that are not neighbours come last."""
+    nb = tables["nb"]
+    order = np.full(27, -1, np.int64)
+    upper = set(upper_ranks)
+    for e in range(14):
+        r = int(rank_of_neighbour[e])
+        order[vid((3, 3, 3), 1 + nb[e][0], 1 + nb[e][1], 1 + nb[e][2])] = 100 + r if r in upper else r
+    order[13] = 50
+    spare = 200
+    for v in range(27):
+        if order[v] < 0:
+            order[v] = spare
+            spare += 1
+    return order.astype(np.int32).reshape(3, 3, 3)
+
+
+def record_rank_cells(rec4, rank_of_neighbour, tables):
+    """Pairs and critical cells of one 128-bit record, each cell as the
+    descending tuple of the ranks of its lower neighbours (x implicit, () is
+    x).  Returns (set of (tail, head), set of critical cells)."""
+    w = [int(a) for a in rec4]
+    bits = w[0] | (w[1] << 32) | (w[2] << 64) | (w[3] << 96)
+    r = [int(x) for x in rank_of_neighbour]
+    et, tri, tt, tet = tables["edge_tris"], tables["tri"], tables["tri_tets"], tables["tet"]
+
+    def cell(*es):
+        return tuple(sorted((r[int(e)] for e in es), reverse=True))
+
+    ef = [(bits >> (4 * e)) & 15 for e in range(14)]
+    tf = [(bits >> (56 + 2 * t)) & 3 for t in range(36)]
+    pairs, paired = set(), set()
+    for e in range(14):
+        if ef[e] == 1:
+            pairs.add(((), cell(e)))
+        elif ef[e] >= 3:
+            pairs.add((cell(e), cell(*tri[et[e][ef[e] - 3]])))
+    for t in range(36):
+        if tf[t]:
+            pairs.add((cell(*tri[t]), cell(*tet[tt[t][tf[t] - 1]])))
+    for a, b in pairs:
+        paired |= {a, b}
+    inl = [e for e in range(14) if ef[e]]
+    cells = {()} | {cell(e) for e in inl}
+    cells |= {cell(a, b) for a, b in tri if ef[a] and ef[b]}
+    cells |= {cell(a, b, c) for a, b, c in tet if ef[a] and ef[b] and ef[c]}
+    return pairs, cells - paired

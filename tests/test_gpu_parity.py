@@ -369,6 +369,31 @@ def test_gradient_hand_worked_cube():
     assert (got == want).all()
 
 
+@pytest.mark.parametrize("case", ["full14", "lower11"])
+@pytest.mark.parametrize("queue", [True, False])
+def test_gradient_hand_worked_stars(case, queue):
+    """The GPU record of the hand-worked 14- and 11-neighbour lower stars
+    (tests/golden/star_hand.md) decodes to the hand-derived pairs and
+    critical cells and equals the oracle's record, both when x's tile queues
+    it and when the tile pairs it in place; the whole 3x3x3 grid matches the
+    oracle too."""
+    import json
+    import os
+    import brute
+    tables = oracle.star_tables()
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "star_hand.json")))
+    c = [x for x in g["cases"] if x["name"] == case][0]
+    o = brute.hand_star_grid(g["rank_of_neighbour"], c["upper_ranks"], tables)
+    want, _, _ = oracle.lower_stars(o, (3, 3, 3))
+    got = dms.discrete_gradient(_dev(o), queue=queue).cpu().numpy().view(np.uint32)
+    assert (got == want).all()
+    pairs, crit = brute.record_rank_cells(got[13], g["rank_of_neighbour"], tables)
+    assert pairs == {(tuple(t), tuple(h)) for t, h in c["pairs"]}
+    assert crit == {tuple(x) for x in c["critical"]}
+    box = dms.discrete_gradient(_dev(o), (1, 1, 1), (2, 2, 2), queue=queue).cpu().numpy().view(np.uint32)
+    assert (box[0] == want[13]).all()
+
+
 # -------------------------------------------------------------- critical
 
 @pytest.mark.parametrize("dims,kind,seed,box", [

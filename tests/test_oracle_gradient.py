@@ -312,3 +312,22 @@ def test_pls_batch_equals_pls_local():
         _, want, an = oracle.pls_local(k)
         assert an == 0
         assert (got[r] == want).all(), r
+
+
+@pytest.mark.parametrize("case", ["full14", "lower11"])
+def test_hand_worked_star(tables, case):
+    """Hand-derived ProcessLowerStars of an interior vertex with all 14
+    neighbours lower (24 tets) and with 11 lower (an annulus lower link)
+    (tests/golden/star_hand.md): the oracle's record of x decodes to exactly
+    the hand-derived pairs and critical cells."""
+    with open(os.path.join(GOLDEN, "star_hand.json")) as fh:
+        g = json.load(fh)
+    c = [x for x in g["cases"] if x["name"] == case][0]
+    rank = g["rank_of_neighbour"]
+    o = brute.hand_star_grid(rank, c["upper_ranks"], tables)
+    rec, _, an = oracle.lower_stars(o, (3, 3, 3), (1, 1, 1), (2, 2, 2))
+    assert an == 0
+    pairs, crit = brute.record_rank_cells(rec[0], rank, tables)
+    want = {(tuple(t), tuple(h)) for t, h in c["pairs"]}
+    assert pairs == want
+    assert crit == {tuple(x) for x in c["critical"]}
