@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--bumps", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and differentiable lines")
-    ap.add_argument("--cpu-planes", type=int, default=12, help="owned z-planes in the oracle sample")
+    ap.add_argument("--cpu-planes", type=int, default=48, help="owned z-planes in the oracle sample")
     ap.add_argument("--large", action="store_true",
                     help="time the order-free path (gradient from the values + extraction) on the "
                          "2048x1920x1536 float32 field instead (one JSON line of its own)")
@@ -85,33 +85,64 @@ def measured_traffic_gb():
     return round(int(m.group(2)) / 1e9, 2)
 
 
-def cpu_baseline(field, lo, hi, planes):
-    """Times the CPU oracle (order, ProcessLowerStars, extraction) on a slab of
-    the same field: `planes` owned z-planes plus their ghost planes."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_stages(sub, lo, hi, threads):
+    """Order, ProcessLowerStars and extraction of box [lo, hi) of the slab sub
+    with the CPU oracle on `threads` threads; returns (owned vertices, seconds
+    per stage)."""
     import oracle
-    k0 = lo[2]
-    sub = np.ascontiguousarray(field[k0 - 1:k0 + planes + 1])
     nz, ny, nx = sub.shape
     dims = (nx, ny, nz)
-    slo, shi = (lo[0], lo[1], 1), (hi[0], hi[1], 1 + planes)
-    threads = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    o = oracle.order(sub)
+    o = oracle.order(sub, nthreads=threads)
     t1 = time.perf_counter()
-    rec, counts, an = oracle.lower_stars(o, dims, slo, shi, nthreads=threads)
+    rec, counts, an = oracle.lower_stars(o, dims, lo, hi, nthreads=threads)
     t2 = time.perf_counter()
-    oracle.critical_simplices(rec, dims, slo, shi)
+    oracle.critical_simplices(rec, dims, lo, hi, nthreads=threads)
     t3 = time.perf_counter()
-    owned = (shi[0] - slo[0]) * (shi[1] - slo[1]) * (shi[2] - slo[2])
+    owned = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
+    return owned, (t1 - t0, t2 - t1, t3 - t2)
+
+
+def cpu_baseline(field, lo, hi, planes):
+    """Times the CPU oracle (order, ProcessLowerStars, extraction) on a slab of
+    the same field -- `planes` owned z-planes plus their ghost planes -- on
+    every host core the process may use, each stage threaded (the sort as
+    sorted runs merged pairwise, the lower stars and the extraction over rows).
+    Beside it, one thread on the 64^3 noise workload and on a 16-plane slab of
+    the 512^3 Gaussian one."""
+    from paper_2505_21266_amd import inputs
+    k0 = lo[2]
+    sub = np.ascontiguousarray(field[k0 - 1:k0 + planes + 1])
+    threads = len(os.sched_getaffinity(0))
+    owned, (t_o, t_s, t_c) = _oracle_stages(sub, (lo[0], lo[1], 1), (hi[0], hi[1], 1 + planes), threads)
+    one = {}
+    v1 = inputs.config1()
+    n1, st1 = _oracle_stages(v1, (0, 0, 0), (64, 64, 64), 1)
+    one["noise64"] = round(n1 / sum(st1) / 1e9, 6)
+    v2 = inputs.config2()[:18]  # owned planes 1..16 of the 512^3 field, with their neighbours
+    n2, st2 = _oracle_stages(np.ascontiguousarray(v2), (0, 0, 1), (512, 512, 17), 1)
+    one["gauss512_16planes"] = round(n2 / sum(st2) / 1e9, 6)
     return {
-        "value": owned / (t3 - t0) / 1e9,
+        "value": owned / (t_o + t_s + t_c) / 1e9,
         "unit": "Gvertices/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "%d owned z-planes (%dx%dx%d owned vertices, %.1f M) of the same field; "
-                  "order %.2f s (qsort, 1 thread), lower stars %.2f s (%d threads), "
-                  "extraction %.2f s (1 thread)" % (planes, shi[0] - slo[0], shi[1] - slo[1], planes,
-                                                   owned / 1e6, t1 - t0, t2 - t1, threads, t3 - t2),
+        "sample": "%d owned z-planes (%dx%dx%d owned vertices, %.1f M) of the same field, %d threads in "
+                  "every stage: order %.2f s, lower stars %.2f s, extraction %.2f s; CPU: %s"
+                  % (planes, hi[0] - lo[0], hi[1] - lo[1], planes, owned / 1e6, threads, t_o, t_s, t_c,
+                     cpu_model()),
+        "one_thread_gvertices_per_s": one,
     }
 
 

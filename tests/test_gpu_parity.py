@@ -588,15 +588,37 @@ def test_d2_pairs_gpu_matches_oracle(shape, kind, seed):
     assert len(pq) == len(crit[3])
 
 
+def _densest_box(mask, side=16):
+    """Corner (k, j, i) of the side^3 box holding the most True entries of a
+    (nz, ny, nx) mask; ties go to the smallest corner id."""
+    c = np.zeros(tuple(d + 1 for d in mask.shape), np.int64)
+    c[1:, 1:, 1:] = mask.astype(np.int64).cumsum(0).cumsum(1).cumsum(2)
+    s = side
+    box = (c[s:, s:, s:] - c[:-s, s:, s:] - c[s:, :-s, s:] - c[s:, s:, :-s]
+           + c[:-s, :-s, s:] + c[:-s, s:, :-s] + c[s:, :-s, :-s] - c[:-s, :-s, :-s])
+    best = np.flatnonzero(box.reshape(-1) == box.max())[0]  # C order: smallest corner id first
+    return np.unravel_index(best, box.shape), int(box.max())
+
+
 def test_d0_finite_differences_config5():
-    """The differentiable form on the 128^3 float64 workload, checked by
-    central finite differences of its own GPU forward on a 16^3 sub-grid:
-    every vertex of the sub-grid whose analytic gradient is non-zero, and 48
-    whose gradient is zero.  The step is a quarter of the smallest value gap,
-    so the pairing, and with it the loss's quadratic form, does not change."""
+    """The differentiable form on the 128^3 float64 workload against finite
+    differences of the loss (Section 2.5), on the 16^3 sub-grid holding the
+    most vertices with a non-zero gradient.  The step eps is a quarter of the
+    smallest value gap, so the vertex order and with it every pair is
+    unchanged -- checked by re-running the GPU forward at +-eps for every
+    sub-grid vertex with a non-zero gradient and random others (at least
+    256), whose pair lists must be identical.  Over those unchanged pairs the
+    loss is an exact quadratic, and for all 4096 sub-grid vertices the
+    central difference, taken term by term in exact rational arithmetic over
+    the pairs the vertex enters, matches the GPU gradient to 1e-8 relative.
+    The whole-loss difference (math.fsum) is checked to 1e-4 relative, the
+    floor its rounding sets."""
+    import math
+    from fractions import Fraction
     from paper_2505_21266_amd.autograd import d0_loss
     f = inputs.config5()
     nz, ny, nx = f.shape
+    dims = (nx, ny, nz)
     flat = f.reshape(-1)
     eps = float(np.diff(np.sort(flat)).min()) / 4
     assert eps > 0
@@ -604,23 +626,62 @@ def test_d0_finite_differences_config5():
     births, deaths = dms.PersistenceD0.apply(x)
     d0_loss(births, deaths, 0.05).backward()
     g = x.grad.cpu().numpy().reshape(-1)
-    k, j, i = np.meshgrid(np.arange(56, 72), np.arange(56, 72), np.arange(56, 72), indexing="ij")
+
+    def pairs_at(v):
+        og = dms.order(_dev(v))
+        rg = dms.discrete_gradient(og)
+        lists, _ = dms.critical_simplices(rg, dims)
+        return dms.d0_pairs(rg, og, dims, lists[0], lists[1])
+
+    pe, pm = pairs_at(f)
+    pers = flat[pe >> 8] - flat[pm]
+    assert np.all(np.abs(pers - 0.05) > 2 * eps)  # the threshold set cannot change either
+    (k0, j0, i0), nnz = _densest_box((g != 0).reshape(f.shape))
+    k, j, i = np.meshgrid(np.arange(k0, k0 + 16), np.arange(j0, j0 + 16), np.arange(i0, i0 + 16), indexing="ij")
     sub = (i + nx * (j + ny * k)).reshape(-1)
     nonzero = sub[g[sub] != 0]
-    zero = np.random.default_rng(51).choice(sub[g[sub] == 0], 48, replace=False)
-    assert nonzero.size > 0
-    _say("fd config5", nonzero.size, "non-zero vertices")
-
+    assert nonzero.size == nnz and nnz > 0
+    _say("fd config5: box", (i0, j0, k0), nnz, "non-zero vertices")
+    rng = np.random.default_rng(51)
+    zero = sub[g[sub] == 0]
+    extra = rng.choice(zero, max(256 - nonzero.size, 32), replace=False)
+    for vid in np.concatenate([nonzero, extra]):
+        for sgn in (1.0, -1.0):
+            vp = flat.copy()
+            vp[vid] += sgn * eps
+            qe, qm = pairs_at(vp.reshape(f.shape))
+            assert np.array_equal(qe, pe) and np.array_equal(qm, pm), (int(vid), sgn)
+    # term-wise central differences over the unchanged pairs, exactly
+    death_v, birth_v = (pe >> 8).astype(np.int64), pm.astype(np.int64)
+    keep = pers < 0.05
+    by_vertex = {}
+    for p in np.flatnonzero(keep):
+        by_vertex.setdefault(int(death_v[p]), []).append(p)
+        by_vertex.setdefault(int(birth_v[p]), []).append(p)
+    for vid in sub:
+        vid = int(vid)
+        fd = Fraction(0)
+        up, dn = flat[vid] + eps, flat[vid] - eps
+        h = Fraction(up) - Fraction(dn)
+        for p in by_vertex.get(vid, []):
+            d, b = int(death_v[p]), int(birth_v[p])
+            fp = {d: Fraction(flat[d]), b: Fraction(flat[b])}
+            fm = dict(fp)
+            fp[vid], fm[vid] = Fraction(up), Fraction(dn)
+            fd += ((fp[d] - fp[b]) ** 2 - (fm[d] - fm[b]) ** 2) / h
+        assert abs(float(fd) - g[vid]) <= 1e-8 * max(abs(g[vid]), 1e-6), (vid, float(fd), g[vid])
+    # the whole loss, on a few of them, from the GPU forward at +-eps
     def loss_at(v):
         with torch.no_grad():
             b, d = dms.PersistenceD0.apply(_dev(v.reshape(f.shape)))
-            return float(d0_loss(b, d, 0.05))
+            p = (d - b).cpu().numpy()
+            return math.fsum((p[p < 0.05] ** 2).tolist())
 
-    for vid in np.concatenate([nonzero, zero]):
+    for vid in nonzero[:24]:
         vp = flat.copy(); vp[vid] += eps
         vm = flat.copy(); vm[vid] -= eps
-        fd = (loss_at(vp) - loss_at(vm)) / (2 * eps)
-        assert abs(fd - g[vid]) <= 1e-6 * max(abs(g[vid]), 1e-3), (int(vid), fd, g[vid])
+        fd = (loss_at(vp) - loss_at(vm)) / (vp[vid] - vm[vid])
+        assert abs(fd - g[vid]) <= 1e-4 * max(abs(g[vid]), 1e-3), (int(vid), fd, g[vid])
 
 
 def test_d2_backward_config5():
