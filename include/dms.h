@@ -182,6 +182,28 @@ int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3], const int
                            size_t workspace_bytes, uint32_t *dev_flags, void *stream);
 
 /* ----------------------------------------------------------------------------
+ * The same extraction with no workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  The workspace is a device
+ * array inside the library, one per GPU, held until the process ends:
+ * about 16.4 MB, enough for boxes of up to 160 * 1024 tiles of 1024
+ * records (167,772,160 vertices).  It never allocates or frees memory; the
+ * array's address on the current device is taken by dms_init.  Calls on one
+ * GPU share that array: two calls that overlap in time on one GPU (on
+ * different streams) race and give undefined lists; calls in one stream's
+ * order do not.  Every word the kernels read is first written by the same
+ * call, so nothing carries over from an earlier call.  Arguments as for
+ * dms_critical_simplices.
+ * Errors: DMS_E_ARG, DMS_E_SIZE (box beyond the limit above, or a grid
+ * beyond 2^40 vertices), DMS_E_UNSUPPORTED, DMS_E_NOT_INITIALISED (dms_init
+ * has not run on the current device), DMS_E_HIP.
+ * -------------------------------------------------------------------------- */
+int dms_critical_simplices_noalloc(const uint32_t *rec, const int64_t dims[3], const int64_t lo[3],
+                                   const int64_t hi[3], int64_t *crit0, int64_t *crit1, int64_t *crit2,
+                                   int64_t *crit3, const int64_t cap[4], int64_t *counts, uint32_t *dev_flags,
+                                   void *stream);
+
+/* ----------------------------------------------------------------------------
  * Values of simplices -- Section 2.5: a persistence pair is embedded at
  * (f(birth simplex), f(death simplex)), where f of a simplex is the value of
  * its highest vertex.  out[i] = values[codes[i] >> 8] as float64 (codes as

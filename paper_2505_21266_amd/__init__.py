@@ -26,7 +26,8 @@ SYMBOLS = ("dms_status_str", "dms_version", "dms_init", "dms_star_tables", "dms_
            "dms_order", "dms_gradient_workspace_size", "dms_discrete_gradient",
            "dms_discrete_gradient_values",
            "dms_critical_workspace_size",
-           "dms_critical_simplices", "dms_simplex_values", "dms_gradient_backward_workspace_size",
+           "dms_critical_simplices", "dms_critical_simplices_noalloc", "dms_simplex_values",
+           "dms_gradient_backward_workspace_size",
            "dms_gradient_backward", "dms_d0_pairs_host",
            "dms_batch_create", "dms_batch_workspace_size", "dms_batch_total", "dms_batch_variant",
            "dms_batch_run", "dms_batch_destroy", "dms_d0_workspace_size", "dms_d0_triplets",
@@ -68,6 +69,7 @@ def lib():
     L.dms_critical_workspace_size.argtypes = [P, P, P]
     L.dms_critical_workspace_size.restype = SZ
     L.dms_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
+    L.dms_critical_simplices_noalloc.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
     L.dms_simplex_values.argtypes = [P, I, I64, P, I64, P, P]
     L.dms_gradient_backward_workspace_size.argtypes = [I64]
     L.dms_gradient_backward_workspace_size.restype = SZ
@@ -93,7 +95,7 @@ def lib():
     L.dms_d2_workspace_size.restype = SZ
     L.dms_d2_triplets.argtypes = [P, P, P, P, I64, P, I64, P, P, P, P, P, P, SZ, P, P]
     L.dms_d2_pairs_sorted_host.argtypes = [P, P, P, I64, P, I64, P, P, I64, P]
-    for f in ("dms_init", "dms_simplex_values", "dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_discrete_gradient_values",
+    for f in ("dms_init", "dms_critical_simplices_noalloc", "dms_simplex_values", "dms_star_tables", "dms_order", "dms_discrete_gradient", "dms_discrete_gradient_values",
               "dms_critical_simplices", "dms_d0_triplets", "dms_d0_pairs_sorted_host", "dms_critical_sort",
               "dms_d2_triplets", "dms_d2_pairs_sorted_host",
               "dms_gradient_backward", "dms_d0_pairs_host", "dms_batch_create", "dms_batch_variant",
@@ -364,6 +366,35 @@ def critical_simplices(rec, dims, lo=None, hi=None, cap=None, flags=None, counts
                                     ws.numel(), _ptr(flags), st), "dms_critical_simplices")
     if own_flags:
         check_flags(flags)
+    return lists, counts
+
+
+def critical_simplices_noalloc(rec, dims, cap, lo=None, hi=None, lists=None, counts=None, flags=None):
+    """The extraction with the library's own scratch array
+    (dms_critical_simplices_noalloc: no workspace, nothing allocated by the
+    library).  cap: per-dimension capacities; lists: four int64 tensors of
+    those capacities (allocated here when None).  Returns (lists, counts);
+    the caller checks flags (DMS_FLAG_CAPACITY) after a sync."""
+    import torch
+    _require_gpu(rec, "rec")
+    dev = rec.device
+    init(dev)
+    lo, hi = _box(dims, lo, hi)
+    d, dp = _arr3(dims)
+    l, lp = _arr3(lo)
+    h, hp = _arr3(hi)
+    capa = np.ascontiguousarray(np.asarray(cap, dtype=np.int64).reshape(4))
+    if lists is None:
+        lists = [torch.empty(int(max(c, 0)), dtype=torch.int64, device=dev) for c in capa]
+    if counts is None:
+        counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    if flags is None:
+        flags = new_flags(dev)
+    _check(lib().dms_critical_simplices_noalloc(_ptr(rec), dp, lp, hp, _ptr(lists[0]), _ptr(lists[1]),
+                                                _ptr(lists[2]), _ptr(lists[3]),
+                                                capa.ctypes.data_as(ctypes.c_void_p), _ptr(counts),
+                                                _ptr(flags), _stream(rec)),
+           "dms_critical_simplices_noalloc")
     return lists, counts
 
 

@@ -56,7 +56,7 @@ inline int launch_status()
     return e == hipSuccess ? DMS_OK : DMS_E_HIP;
 }
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // -------------------------------------------------------------- device side
 

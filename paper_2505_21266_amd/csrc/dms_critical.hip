@@ -11,6 +11,8 @@
 //         order, written at tile offset + scan offset as int64 codes
 //         (max vertex id << 8) | local index.  A tile with more than kCand
 //         such records is re-read whole.
+#include <atomic>
+
 #include "dms_common.hpp"
 #include "dms_internal.hpp"
 #include "dms_scan.hpp"
@@ -563,7 +565,7 @@ struct CritLayout {
     size_t partials, cand, ncand, total;
 };
 
-CritLayout crit_layout(int64_t ntiles)
+constexpr CritLayout crit_layout(int64_t ntiles)
 {
     const int64_t len = 4 * ntiles + 1;
     CritLayout L{};
@@ -573,6 +575,61 @@ CritLayout crit_layout(int64_t ntiles)
     L.ncand = off; off += align_up((size_t)ntiles * 4, 256);
     L.total = off;
     return L;
+}
+
+// Allocation-free extraction: its workspace lives in this file-scope device
+// array, one per device, for boxes of up to kNoAllocTiles tiles of
+// kTileRecs records.  Host code reaches the array only through the address
+// hipGetSymbolAddress gives on each device (init_critical_scratch).
+constexpr int64_t kNoAllocTiles = 160 * 1024;  // boxes of up to 167,772,160 vertices
+constexpr size_t kNoAllocBytes = crit_layout(kNoAllocTiles).total;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+static std::atomic<char *> g_scratch[64];  // per device: the array's device address
+
+// Enqueues the extraction of box [lo, hi) into crit0..3 with the workspace
+// ws (crit_layout of the box's tiles); arguments already checked.
+int launch_critical(const uint32_t *rec, const int64_t *dims, const int64_t *lo, const int64_t *hi,
+                    int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, const int64_t *cap,
+                    int64_t *counts, char *workspace, uint32_t *dev_flags, hipStream_t s)
+{
+    const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
+    const int64_t nbox = w0 * w1 * w2;
+    const int64_t ntiles = (nbox + kTileRecs - 1) / kTileRecs;
+    const int64_t len = 4 * ntiles + 1;
+    const CritLayout L = crit_layout(ntiles);
+    uint64_t *tc = (uint64_t *)workspace;
+    uint64_t *partials = (uint64_t *)(workspace + L.partials);
+    uint16_t *cand = (uint16_t *)(workspace + L.cand);
+    uint32_t *ncand = (uint32_t *)(workspace + L.ncand);
+    if (ntiles == 0) {
+        hipLaunchKernelGGL(k_crit_empty, dim3(1), dim3(64), 0, s, counts);
+        return launch_status();
+    }
+    hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
+                       nbox, tc, ntiles, cand, ncand);
+    exclusive_scan<uint64_t>(tc, len, partials, s);
+    hipLaunchKernelGGL(k_crit_fill, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
+                       nbox, tc, ntiles, cand, ncand, w0, w1, lo[0], lo[1], lo[2], dims[0], dims[1],
+                       crit0, crit1, crit2, crit3, cap[0], cap[1], cap[2], cap[3]);
+    hipLaunchKernelGGL(k_crit_finish, dim3(1), dim3(64), 0, s, tc, ntiles, counts, cap[0], cap[1],
+                       cap[2], cap[3], dev_flags);
+    return launch_status();
+}
+
+// Argument checks shared by both extraction entry points.
+int check_critical_args(const uint32_t *rec, const int64_t *dims, const int64_t *lo, const int64_t *hi,
+                        int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, const int64_t *cap,
+                        const int64_t *counts, const uint32_t *dev_flags)
+{
+    if (!box_valid(dims, lo, hi) || !cap || !counts || !dev_flags) return DMS_E_ARG;
+    if (!grid_size_values_ok(dims)) return DMS_E_SIZE;
+    for (int d = 0; d < 4; ++d)
+        if (cap[d] < 0) return DMS_E_ARG;
+    if ((cap[0] && !crit0) || (cap[1] && !crit1) || (cap[2] && !crit2) || (cap[3] && !crit3))
+        return DMS_E_ARG;
+    const int64_t nbox = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+    if (nbox > 0 && !rec) return DMS_E_ARG;
+    return DMS_OK;
 }
 
 size_t critical_batch_workspace_size(int64_t n, int nfields)
@@ -607,9 +664,18 @@ int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, i
     return launch_status();
 }
 
+int init_critical_scratch()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DMS_E_HIP;
+    if (g_scratch[dev].load()) return DMS_OK;
+    char *ptr = nullptr;
+    if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DMS_E_HIP;
+    g_scratch[dev].store(ptr);
+    return DMS_OK;
+}
+
 }  // namespace dms
-
-
 
 extern "C" size_t dms_critical_workspace_size(const int64_t dims[3], const int64_t lo[3],
                                               const int64_t hi[3])
@@ -627,37 +693,30 @@ extern "C" int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3]
                                       uint32_t *dev_flags, void *stream)
 {
     using namespace dms;
-    if (!box_valid(dims, lo, hi) || !cap || !counts || !dev_flags) return DMS_E_ARG;
-    if (!grid_size_values_ok(dims)) return DMS_E_SIZE;
-    for (int d = 0; d < 4; ++d)
-        if (cap[d] < 0) return DMS_E_ARG;
-    if ((cap[0] && !crit0) || (cap[1] && !crit1) || (cap[2] && !crit2) || (cap[3] && !crit3))
-        return DMS_E_ARG;
-    const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
-    const int64_t nbox = w0 * w1 * w2;
-    if (nbox > 0 && !rec) return DMS_E_ARG;
+    if (const int st = check_critical_args(rec, dims, lo, hi, crit0, crit1, crit2, crit3, cap, counts, dev_flags))
+        return st;
     const size_t need = dms_critical_workspace_size(dims, lo, hi);
     if (!workspace || workspace_bytes < need) return DMS_E_WORKSPACE;
     if (const int dc = device_check()) return dc;
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t ntiles = (nbox + kTileRecs - 1) / kTileRecs;
-    const int64_t len = 4 * ntiles + 1;
-    const CritLayout L = crit_layout(ntiles);
-    uint64_t *tc = (uint64_t *)workspace;
-    uint64_t *partials = (uint64_t *)((char *)workspace + L.partials);
-    uint16_t *cand = (uint16_t *)((char *)workspace + L.cand);
-    uint32_t *ncand = (uint32_t *)((char *)workspace + L.ncand);
-    if (ntiles == 0) {
-        hipLaunchKernelGGL(k_crit_empty, dim3(1), dim3(64), 0, s, counts);
-        return launch_status();
-    }
-    hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       nbox, tc, ntiles, cand, ncand);
-    exclusive_scan<uint64_t>(tc, len, partials, s);
-    hipLaunchKernelGGL(k_crit_fill, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       nbox, tc, ntiles, cand, ncand, w0, w1, lo[0], lo[1], lo[2], dims[0], dims[1],
-                       crit0, crit1, crit2, crit3, cap[0], cap[1], cap[2], cap[3]);
-    hipLaunchKernelGGL(k_crit_finish, dim3(1), dim3(64), 0, s, tc, ntiles, counts, cap[0], cap[1],
-                       cap[2], cap[3], dev_flags);
-    return launch_status();
+    return launch_critical(rec, dims, lo, hi, crit0, crit1, crit2, crit3, cap, counts, (char *)workspace,
+                           dev_flags, (hipStream_t)stream);
+}
+
+extern "C" int dms_critical_simplices_noalloc(const uint32_t *rec, const int64_t dims[3], const int64_t lo[3],
+                                              const int64_t hi[3], int64_t *crit0, int64_t *crit1,
+                                              int64_t *crit2, int64_t *crit3, const int64_t cap[4],
+                                              int64_t *counts, uint32_t *dev_flags, void *stream)
+{
+    using namespace dms;
+    if (const int st = check_critical_args(rec, dims, lo, hi, crit0, crit1, crit2, crit3, cap, counts, dev_flags))
+        return st;
+    const int64_t nbox = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+    if ((nbox + kTileRecs - 1) / kTileRecs > kNoAllocTiles) return DMS_E_SIZE;
+    if (const int dc = device_check()) return dc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DMS_E_HIP;
+    char *ws = g_scratch[dev].load();
+    if (!ws) return DMS_E_NOT_INITIALISED;
+    return launch_critical(rec, dims, lo, hi, crit0, crit1, crit2, crit3, cap, counts, ws, dev_flags,
+                           (hipStream_t)stream);
 }

@@ -1102,4 +1102,8 @@ extern "C" int dms_discrete_gradient_values(const void *values, int dtype, const
                                          (hipStream_t)stream);
 }
 
-extern "C" int dms_init(void *stream) { return dms::init_tables((hipStream_t)stream); }
+extern "C" int dms_init(void *stream)
+{
+    if (const int st = dms::init_tables((hipStream_t)stream)) return st;
+    return dms::init_critical_scratch();
+}

@@ -23,6 +23,9 @@ constexpr int kTileX[kGradVariants] = {64, 32, 16};
 // Checks the device and fills its lower-star tables once (one
 // synchronisation of s); later calls return at once.
 int init_tables(hipStream_t s);
+// Takes the current device's address of the allocation-free extraction's
+// scratch array (once per device).
+int init_critical_scratch();
 // ws: gradient_workspace_size(owned vertices) bytes for the queue of
 // general vertices, or null (every tile then pairs its own).
 size_t gradient_workspace_size(int64_t owned);

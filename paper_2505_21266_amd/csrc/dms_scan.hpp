@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(T *data, int64_t len
     }
 }
 
-inline size_t scan_partials_bytes(int64_t len, size_t elem)
+constexpr size_t scan_partials_bytes(int64_t len, size_t elem)
 {
     const int64_t blocks = (len + kScanChunk - 1) / kScanChunk;
     return align_up((size_t)(blocks > 0 ? blocks : 1) * elem, 256);

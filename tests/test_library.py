@@ -107,6 +107,15 @@ def test_argument_errors(L):
     assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, c1p, fake, fake,
                                     1 << 20, fake, None) == 1
     assert L.dms_critical_workspace_size(dp, lp, badp) == 0
+    # allocation-free extraction: same argument checks, and boxes past its
+    # scratch array (160 Ki tiles of 1024 records) are refused
+    assert L.dms_critical_simplices_noalloc(fake, dp, lp, hp, None, None, None, None, ncapp, fake, fake,
+                                            None) == 1
+    assert L.dms_critical_simplices_noalloc(fake, dp, lp, hp, None, None, None, None, capp, fake, None,
+                                            None) == 1
+    big, bigp = _a3([1024, 1024, 161])
+    assert L.dms_critical_simplices_noalloc(fake, bigp, lp, bigp, None, None, None, None, capp, fake, fake,
+                                            None) == 2
     # backward
     need = L.dms_gradient_backward_workspace_size(3)
     assert need >= 6 * 16
@@ -146,6 +155,8 @@ def test_no_device_is_unsupported(L):
     need = L.dms_gradient_backward_workspace_size(3)
     assert L.dms_gradient_backward(fake, fake, fake, fake, 3, fake, 10, fake, need, None) == 4
     assert L.dms_simplex_values(fake, 0, 10, fake, 3, fake, None) == 4
+    assert L.dms_critical_simplices_noalloc(fake, dp, lp, hp, None, None, None, None, capp, fake, fake,
+                                            None) == 4
     out = P()
     assert L.dms_batch_create(d.ctypes.data_as(P), 1, 0, 0, None, ctypes.byref(out)) == 4
     assert not out.value
