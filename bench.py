@@ -26,7 +26,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # algorithmic bytes per owned vertex of each stage (what the method must move)
-ALG_BYTES = {"order": 8.0, "gradient": 20.0, "critical": 16.0}
+# (gradient: order read + record write + critical-mask bit; critical: see MASK_BYTES)
+MASK_BYTES = 1.0 / 8.0
+ALG_BYTES = {"order": 8.0, "gradient": 20.0 + MASK_BYTES, "critical": 16.0}
 
 
 def parse():
@@ -260,8 +262,9 @@ def bench_large(args, dev):
                                                                     dms._arr3(hi)[1])),
                       dtype=torch.uint8, device=dev)
     flags = dms.new_flags(dev)
-    dms.discrete_gradient_values(values, out=rec, workspace=gws, flags=flags, check=False)
-    lists, counts = dms.critical_simplices(rec, dims)
+    mask = dms.critical_mask(n, dev)
+    dms.discrete_gradient_values(values, out=rec, workspace=gws, flags=flags, check=False, mask=mask)
+    lists, counts = dms.critical_simplices(rec, dims, mask=mask)
     cap = counts.cpu().numpy().copy()
     counts_t = torch.zeros(4, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -269,10 +272,10 @@ def bench_large(args, dev):
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        dms.discrete_gradient_values(values, out=rec, workspace=gws, flags=flags, check=False)
+        dms.discrete_gradient_values(values, out=rec, workspace=gws, flags=flags, check=False, mask=mask)
         if ev is not None:
             ev[1].record(stream)
-        dms.critical_simplices(rec, dims, cap=cap, flags=flags, counts=counts_t)
+        dms.critical_simplices(rec, dims, cap=cap, flags=flags, counts=counts_t, mask=mask)
         if ev is not None:
             ev[2].record(stream)
 
@@ -339,12 +342,14 @@ def main():
     rec = torch.empty((owned, 4), dtype=torch.int32, device=dev)
     flags = dms.new_flags(dev)
     gws = dms.gradient_workspace(order_t, lo, hi)
+    mask = dms.critical_mask(owned, dev)
     # capacities from one exact run (the counts do not change between steps)
     dms.order(values, out=order_t)
-    dms.discrete_gradient(order_t, lo, hi, out=rec, workspace=gws)
-    lists, counts = dms.critical_simplices(rec, dims, lo, hi)
+    dms.discrete_gradient(order_t, lo, hi, out=rec, workspace=gws, mask=mask)
+    lists, counts = dms.critical_simplices(rec, dims, lo, hi, mask=mask)
     cap = counts.cpu().numpy().copy()
     counts_t = torch.zeros(4, dtype=torch.int64, device=dev)
+    flagged = int(np.unpackbits(mask.cpu().numpy().view(np.uint8)).sum())
 
     def step(ev=None):
         if ev is not None:
@@ -352,10 +357,10 @@ def main():
         dms.order(values, out=order_t, flags=flags, check=False)
         if ev is not None:
             ev[1].record(stream)
-        dms.discrete_gradient(order_t, lo, hi, out=rec, workspace=gws)
+        dms.discrete_gradient(order_t, lo, hi, out=rec, workspace=gws, mask=mask)
         if ev is not None:
             ev[2].record(stream)
-        dms.critical_simplices(rec, dims, lo, hi, cap=cap, flags=flags, counts=counts_t)
+        dms.critical_simplices(rec, dims, lo, hi, cap=cap, flags=flags, counts=counts_t, mask=mask)
         if ev is not None:
             ev[3].record(stream)
 
@@ -385,6 +390,14 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_values_gradient = ev0.elapsed_time(ev1) / 3
+    # the extraction without the mask (every record read), for comparison
+    dms.critical_simplices(rec, dims, lo, hi, cap=cap, flags=flags, counts=counts_t)
+    ev0.record(stream)
+    for _ in range(3):
+        dms.critical_simplices(rec, dims, lo, hi, cap=cap, flags=flags, counts=counts_t)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_critical_unmasked = ev0.elapsed_time(ev1) / 3
     # the extracted lists in filtration order (Section 2.1; the local sort
     # after extraction), all four dimensions; not part of the step
     sorted_lists = [torch.empty_like(lists[d]) for d in range(4)]
@@ -404,8 +417,11 @@ def main():
 
     # dominant call: dms_discrete_gradient (k_queue_reset + k_gradient + k_gradient_queue on the
     # same stream; the events bracket exactly these launches)
+    stage_bytes = {k: ALG_BYTES[k] * owned for k in ALG_BYTES}
+    # the masked extraction reads the mask and the flagged records only
+    stage_bytes["critical"] = MASK_BYTES * owned + 16.0 * flagged
     dom = "gradient"
-    achieved = ALG_BYTES[dom] * owned / (ms[dom] / 1e3) / 1e9
+    achieved = stage_bytes[dom] / (ms[dom] / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic_gb(),
@@ -430,9 +446,10 @@ def main():
                    "owned_vertices": owned, "critical_counts": [int(c) for c in cap]},
         "stage_ms": {k: round(v, 3) for k, v in ms.items()},
         "gradient_from_values_ms": round(ms_values_gradient, 3),
+        "critical_unmasked_ms": round(ms_critical_unmasked, 3),
+        "flagged_records": flagged,
         "critical_sort_ms": round(ms_critical_sort, 3),
-        "stage_frac_hbm": {k: round(ALG_BYTES[k] * owned / (ms[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
-                           for k in ms},
+        "stage_frac_hbm": {k: round(stage_bytes[k] / (ms[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 4) for k in ms},
         "roofline": roofline,
         "input_gen_s": round(t_gen, 1),
     }

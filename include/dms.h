@@ -132,12 +132,16 @@ int dms_order(const void *values, int dtype, int64_t n, int32_t *order, void *wo
  * star needs the full pairing loop are gathered and paired in dense waves;
  * or NULL (with workspace_bytes 0), in which case they are paired where
  * they are found -- the same records, slower on smooth fields.
+ * critical_mask: NULL, or ceil(nbox / 32) device uint32 (nbox = vertices of
+ * the box) that receive one bit per record in box order, bit r % 32 of word
+ * r / 32 set iff L(x) of record r holds a critical cell; every word is
+ * written.  dms_critical_simplices reads only the records it flags.
  * Errors: DMS_E_ARG (null order/rec, dims < 1, box outside the grid),
  * DMS_E_SIZE, DMS_E_WORKSPACE (non-null workspace below the size), DMS_E_HIP.
  * -------------------------------------------------------------------------- */
 size_t dms_gradient_workspace_size(const int64_t dims[3], const int64_t lo[3], const int64_t hi[3]);
 int dms_discrete_gradient(const int32_t *order, const int64_t dims[3], const int64_t lo[3],
-                          const int64_t hi[3], uint32_t *rec, void *workspace,
+                          const int64_t hi[3], uint32_t *rec, uint32_t *critical_mask, void *workspace,
                           size_t workspace_bytes, void *stream);
 
 /* ----------------------------------------------------------------------------
@@ -156,8 +160,8 @@ int dms_discrete_gradient(const int32_t *order, const int64_t dims[3], const int
  * -------------------------------------------------------------------------- */
 int dms_discrete_gradient_values(const void *values, int dtype, const int64_t dims[3],
                                  const int64_t lo[3], const int64_t hi[3], uint32_t *rec,
-                                 void *workspace, size_t workspace_bytes, uint32_t *dev_flags,
-                                 void *stream);
+                                 uint32_t *critical_mask, void *workspace, size_t workspace_bytes,
+                                 uint32_t *dev_flags, void *stream);
 
 /* ----------------------------------------------------------------------------
  * Critical simplices -- Section 2.6 (zero-persistence skip: every
@@ -173,13 +177,18 @@ int dms_discrete_gradient_values(const void *values, int dtype, const int64_t di
  * room for cap[d] codes ([host] cap); counts: 4 device int64, always the
  * exact totals.  When a total exceeds its capacity the list is truncated
  * and DMS_FLAG_CAPACITY is set.
+ * critical_mask: NULL (every record is read), or the mask the gradient call
+ * wrote with these records: only records whose bit is set are read, the
+ * others count as holding no critical cell (Section 2.6: most vertices hold
+ * none, so the extraction then reads about 1/128 of the record bytes).  A
+ * mask from other records gives undefined lists.
  * Errors: DMS_E_ARG, DMS_E_SIZE, DMS_E_WORKSPACE, DMS_E_HIP.
  * -------------------------------------------------------------------------- */
 size_t dms_critical_workspace_size(const int64_t dims[3], const int64_t lo[3], const int64_t hi[3]);
-int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3], const int64_t lo[3],
-                           const int64_t hi[3], int64_t *crit0, int64_t *crit1, int64_t *crit2,
-                           int64_t *crit3, const int64_t cap[4], int64_t *counts, void *workspace,
-                           size_t workspace_bytes, uint32_t *dev_flags, void *stream);
+int dms_critical_simplices(const uint32_t *rec, const uint32_t *critical_mask, const int64_t dims[3],
+                           const int64_t lo[3], const int64_t hi[3], int64_t *crit0, int64_t *crit1,
+                           int64_t *crit2, int64_t *crit3, const int64_t cap[4], int64_t *counts,
+                           void *workspace, size_t workspace_bytes, uint32_t *dev_flags, void *stream);
 
 /* ----------------------------------------------------------------------------
  * The same extraction with no workspace argument, for callers that cannot
@@ -198,9 +207,10 @@ int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3], const int
  * beyond 2^40 vertices), DMS_E_UNSUPPORTED, DMS_E_NOT_INITIALISED (dms_init
  * has not run on the current device), DMS_E_HIP.
  * -------------------------------------------------------------------------- */
-int dms_critical_simplices_noalloc(const uint32_t *rec, const int64_t dims[3], const int64_t lo[3],
-                                   const int64_t hi[3], int64_t *crit0, int64_t *crit1, int64_t *crit2,
-                                   int64_t *crit3, const int64_t cap[4], int64_t *counts, uint32_t *dev_flags,
+int dms_critical_simplices_noalloc(const uint32_t *rec, const uint32_t *critical_mask,
+                                   const int64_t dims[3], const int64_t lo[3], const int64_t hi[3],
+                                   int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3,
+                                   const int64_t cap[4], int64_t *counts, uint32_t *dev_flags,
                                    void *stream);
 
 /* ----------------------------------------------------------------------------

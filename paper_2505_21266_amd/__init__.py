@@ -64,12 +64,12 @@ def lib():
     L.dms_order.argtypes = [P, I, I64, P, P, SZ, P, P]
     L.dms_gradient_workspace_size.argtypes = [P, P, P]
     L.dms_gradient_workspace_size.restype = SZ
-    L.dms_discrete_gradient.argtypes = [P, P, P, P, P, P, SZ, P]
-    L.dms_discrete_gradient_values.argtypes = [P, I, P, P, P, P, P, SZ, P, P]
+    L.dms_discrete_gradient.argtypes = [P, P, P, P, P, P, P, SZ, P]
+    L.dms_discrete_gradient_values.argtypes = [P, I, P, P, P, P, P, P, SZ, P, P]
     L.dms_critical_workspace_size.argtypes = [P, P, P]
     L.dms_critical_workspace_size.restype = SZ
-    L.dms_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
-    L.dms_critical_simplices_noalloc.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
+    L.dms_critical_simplices.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, SZ, P, P]
+    L.dms_critical_simplices_noalloc.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P]
     L.dms_simplex_values.argtypes = [P, I, I64, P, I64, P, P]
     L.dms_gradient_backward_workspace_size.argtypes = [I64]
     L.dms_gradient_backward_workspace_size.restype = SZ
@@ -255,11 +255,31 @@ def gradient_workspace(order_t, lo=None, hi=None):
                        dtype=torch.uint8, device=order_t.device)
 
 
-def discrete_gradient(order_t, lo=None, hi=None, out=None, queue=True, workspace=None):
+def critical_mask(nbox, device):
+    """A critical-record mask for a box of nbox vertices: int32 tensor of
+    ceil(nbox / 32) words (one bit per record)."""
+    import torch
+    return torch.empty(max((int(nbox) + 31) // 32, 1), dtype=torch.int32, device=device)
+
+
+def _mask_ptr(mask, nbox):
+    if mask is None:
+        return None
+    import torch
+    if not mask.is_cuda or mask.dtype != torch.int32 or not mask.is_contiguous():
+        raise TypeError("critical mask must be a contiguous int32 GPU tensor")
+    if mask.numel() < (nbox + 31) // 32:
+        raise ValueError("critical mask too small (%d < %d words)" % (mask.numel(), (nbox + 31) // 32))
+    return _ptr(mask)
+
+
+def discrete_gradient(order_t, lo=None, hi=None, out=None, queue=True, workspace=None, mask=None):
     """Lower-star records (dms_discrete_gradient): int32 tensor (nbox, 4)
     holding the 128-bit records (reinterpret as uint32).  queue=False passes
     no workspace (general vertices are then paired inside their tiles);
-    workspace (from gradient_workspace) avoids an allocation per call."""
+    workspace (from gradient_workspace) avoids an allocation per call;
+    mask (from critical_mask) receives the bits of the records that hold a
+    critical cell, for critical_simplices."""
     import torch
     _require_gpu(order_t, "order")
     if order_t.dtype != torch.int32:
@@ -283,7 +303,7 @@ def discrete_gradient(order_t, lo=None, hi=None, out=None, queue=True, workspace
             ws, wbytes = workspace, workspace.numel()
         else:
             ws = torch.empty(wbytes, dtype=torch.uint8, device=order_t.device)
-    _check(lib().dms_discrete_gradient(_ptr(order_t), dp, lp, hp, _ptr(out),
+    _check(lib().dms_discrete_gradient(_ptr(order_t), dp, lp, hp, _ptr(out), _mask_ptr(mask, nbox),
                                        _ptr(ws) if ws is not None else None, wbytes,
                                        _stream(order_t)),
            "dms_discrete_gradient")
@@ -291,10 +311,11 @@ def discrete_gradient(order_t, lo=None, hi=None, out=None, queue=True, workspace
 
 
 def discrete_gradient_values(values, lo=None, hi=None, out=None, queue=True, workspace=None,
-                             flags=None, check=True):
+                             flags=None, check=True, mask=None):
     """Lower-star records straight from the values (dms_discrete_gradient_values):
     the same records as discrete_gradient(order(values)), without the sort.
-    Raises on NaN when check (else the caller reads flags)."""
+    Raises on NaN when check (else the caller reads flags); mask as for
+    discrete_gradient."""
     import torch
     _require_gpu(values, "values")
     dt = _dtype_code(values)
@@ -321,6 +342,7 @@ def discrete_gradient_values(values, lo=None, hi=None, out=None, queue=True, wor
         else:
             ws = torch.empty(wbytes, dtype=torch.uint8, device=values.device)
     _check(lib().dms_discrete_gradient_values(_ptr(values), dt, dp, lp, hp, _ptr(out),
+                                              _mask_ptr(mask, nbox),
                                               _ptr(ws) if ws is not None else None, wbytes,
                                               _ptr(flags), _stream(values)),
            "dms_discrete_gradient_values")
@@ -329,11 +351,13 @@ def discrete_gradient_values(values, lo=None, hi=None, out=None, queue=True, wor
     return out
 
 
-def critical_simplices(rec, dims, lo=None, hi=None, cap=None, flags=None, counts=None):
+def critical_simplices(rec, dims, lo=None, hi=None, cap=None, flags=None, counts=None, mask=None):
     """Critical cells (dms_critical_simplices) as four int64 code tensors.
 
     cap: per-dimension capacities; None sizes the lists exactly (one extra
-    counting call and a sync).  Returns (lists, counts tensor).
+    counting call and a sync).  mask: the critical mask the gradient call
+    wrote with rec (only flagged records are read), or None.  Returns
+    (lists, counts tensor).
     """
     import torch
     _require_gpu(rec, "rec")
@@ -343,6 +367,7 @@ def critical_simplices(rec, dims, lo=None, hi=None, cap=None, flags=None, counts
     l, lp = _arr3(lo)
     h, hp = _arr3(hi)
     L = lib()
+    mp = _mask_ptr(mask, max(0, hi[0] - lo[0]) * max(0, hi[1] - lo[1]) * max(0, hi[2] - lo[2]))
     nbytes = L.dms_critical_workspace_size(dp, lp, hp)
     ws = _ws_crit.get(nbytes, dev)
     if counts is None:
@@ -353,14 +378,14 @@ def critical_simplices(rec, dims, lo=None, hi=None, cap=None, flags=None, counts
     st = _stream(rec)
     if cap is None:
         zc = np.zeros(4, np.int64)
-        _check(L.dms_critical_simplices(_ptr(rec), dp, lp, hp, None, None, None, None,
+        _check(L.dms_critical_simplices(_ptr(rec), mp, dp, lp, hp, None, None, None, None,
                                         zc.ctypes.data_as(ctypes.c_void_p), _ptr(counts), _ptr(ws),
                                         ws.numel(), _ptr(flags), st), "dms_critical_simplices")
         cap = counts.cpu().numpy().copy()
         flags.zero_()
     capa = np.ascontiguousarray(np.asarray(cap, dtype=np.int64).reshape(4))
     lists = [torch.empty(int(max(c, 0)), dtype=torch.int64, device=dev) for c in capa]
-    _check(L.dms_critical_simplices(_ptr(rec), dp, lp, hp, _ptr(lists[0]), _ptr(lists[1]),
+    _check(L.dms_critical_simplices(_ptr(rec), mp, dp, lp, hp, _ptr(lists[0]), _ptr(lists[1]),
                                     _ptr(lists[2]), _ptr(lists[3]),
                                     capa.ctypes.data_as(ctypes.c_void_p), _ptr(counts), _ptr(ws),
                                     ws.numel(), _ptr(flags), st), "dms_critical_simplices")
@@ -369,12 +394,14 @@ def critical_simplices(rec, dims, lo=None, hi=None, cap=None, flags=None, counts
     return lists, counts
 
 
-def critical_simplices_noalloc(rec, dims, cap, lo=None, hi=None, lists=None, counts=None, flags=None):
+def critical_simplices_noalloc(rec, dims, cap, lo=None, hi=None, lists=None, counts=None, flags=None,
+                               mask=None):
     """The extraction with the library's own scratch array
     (dms_critical_simplices_noalloc: no workspace, nothing allocated by the
     library).  cap: per-dimension capacities; lists: four int64 tensors of
-    those capacities (allocated here when None).  Returns (lists, counts);
-    the caller checks flags (DMS_FLAG_CAPACITY) after a sync."""
+    those capacities (allocated here when None); mask as for
+    critical_simplices.  Returns (lists, counts); the caller checks flags
+    (DMS_FLAG_CAPACITY) after a sync."""
     import torch
     _require_gpu(rec, "rec")
     dev = rec.device
@@ -390,7 +417,8 @@ def critical_simplices_noalloc(rec, dims, cap, lo=None, hi=None, lists=None, cou
         counts = torch.zeros(4, dtype=torch.int64, device=dev)
     if flags is None:
         flags = new_flags(dev)
-    _check(lib().dms_critical_simplices_noalloc(_ptr(rec), dp, lp, hp, _ptr(lists[0]), _ptr(lists[1]),
+    mp = _mask_ptr(mask, max(0, hi[0] - lo[0]) * max(0, hi[1] - lo[1]) * max(0, hi[2] - lo[2]))
+    _check(lib().dms_critical_simplices_noalloc(_ptr(rec), mp, dp, lp, hp, _ptr(lists[0]), _ptr(lists[1]),
                                                 _ptr(lists[2]), _ptr(lists[3]),
                                                 capa.ctypes.data_as(ctypes.c_void_p), _ptr(counts),
                                                 _ptr(flags), _stream(rec)),
@@ -586,11 +614,16 @@ def d2_pairs(rec, order_t, dims, crit2, crit3):
 
 
 def gradient_pipeline(values, lo=None, hi=None, cap=None):
-    """order -> discrete gradient -> critical simplices for one field."""
+    """order -> discrete gradient -> critical simplices for one field (the
+    gradient marks the records holding critical cells; the extraction reads
+    only those)."""
     o = order(values)
     dims = dims_of(values)
-    rec = discrete_gradient(o, lo, hi)
-    lists, counts = critical_simplices(rec, dims, lo, hi, cap=cap)
+    blo, bhi = _box(dims, lo, hi)
+    mask = critical_mask(max(0, bhi[0] - blo[0]) * max(0, bhi[1] - blo[1]) * max(0, bhi[2] - blo[2]),
+                         values.device)
+    rec = discrete_gradient(o, lo, hi, mask=mask)
+    lists, counts = critical_simplices(rec, dims, lo, hi, cap=cap, mask=mask)
     return o, rec, lists, counts
 
 

@@ -256,7 +256,10 @@ __device__ __forceinline__ void load_recs(const uint4 *__restrict__ rec, int64_t
 // number per tile (the true number, also beyond kCand).  Records are read
 // striped (record k * kThreads + tid of the tile), so the loads coalesce;
 // the candidates are listed in record order (row k before row k + 1).
-__global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec, int64_t nbox,
+// mask (may be null): bit r set for every record r that holds a critical
+// cell; records with a clear bit count zero cells and are not read.
+__global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec,
+                                                         const uint32_t *__restrict__ mask, int64_t nbox,
                                                          uint64_t *__restrict__ tile_counts,
                                                          int64_t ntiles, uint16_t *__restrict__ cand,
                                                          uint32_t *__restrict__ ncand)
@@ -269,7 +272,9 @@ __global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict
     for (int k = 0; k < kPerThread; ++k) {
         const int64_t r = t0 + k * kThreads + tid;
         uint32_t c[4] = {0, 0, 0, 0};
-        if (r < nbox) {
+        bool take = r < nbox;
+        if (mask && take) take = (mask[r >> 5] >> (uint32_t)(r & 31)) & 1u;
+        if (take) {
             const uint4 w = rec[r];
             count_critical((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), c);
         }
@@ -588,8 +593,8 @@ static std::atomic<char *> g_scratch[64];  // per device: the array's device add
 
 // Enqueues the extraction of box [lo, hi) into crit0..3 with the workspace
 // ws (crit_layout of the box's tiles); arguments already checked.
-int launch_critical(const uint32_t *rec, const int64_t *dims, const int64_t *lo, const int64_t *hi,
-                    int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, const int64_t *cap,
+int launch_critical(const uint32_t *rec, const uint32_t *mask, const int64_t *dims, const int64_t *lo,
+                    const int64_t *hi, int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, const int64_t *cap,
                     int64_t *counts, char *workspace, uint32_t *dev_flags, hipStream_t s)
 {
     const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
@@ -606,7 +611,7 @@ int launch_critical(const uint32_t *rec, const int64_t *dims, const int64_t *lo,
         return launch_status();
     }
     hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       nbox, tc, ntiles, cand, ncand);
+                       mask, nbox, tc, ntiles, cand, ncand);
     exclusive_scan<uint64_t>(tc, len, partials, s);
     hipLaunchKernelGGL(k_crit_fill, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
                        nbox, tc, ntiles, cand, ncand, w0, w1, lo[0], lo[1], lo[2], dims[0], dims[1],
@@ -652,7 +657,7 @@ int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, i
     uint16_t *cand = (uint16_t *)(ws + L.cand);
     uint32_t *ncand = (uint32_t *)(ws + L.ncand);
     hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       n, tc, ntiles, cand, ncand);
+                       (const uint32_t *)nullptr, n, tc, ntiles, cand, ncand);
     exclusive_scan<uint64_t>(tc, len, partials, s);
     hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
                        (const uint4 *)rec, n, tc, ntiles, cand, ncand, foff, nfields, crit[0], crit[1],
@@ -686,7 +691,8 @@ extern "C" size_t dms_critical_workspace_size(const int64_t dims[3], const int64
     return crit_layout((nbox + kTileRecs - 1) / kTileRecs).total;
 }
 
-extern "C" int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3], const int64_t lo[3],
+extern "C" int dms_critical_simplices(const uint32_t *rec, const uint32_t *critical_mask,
+                                      const int64_t dims[3], const int64_t lo[3],
                                       const int64_t hi[3], int64_t *crit0, int64_t *crit1,
                                       int64_t *crit2, int64_t *crit3, const int64_t cap[4],
                                       int64_t *counts, void *workspace, size_t workspace_bytes,
@@ -698,11 +704,13 @@ extern "C" int dms_critical_simplices(const uint32_t *rec, const int64_t dims[3]
     const size_t need = dms_critical_workspace_size(dims, lo, hi);
     if (!workspace || workspace_bytes < need) return DMS_E_WORKSPACE;
     if (const int dc = device_check()) return dc;
-    return launch_critical(rec, dims, lo, hi, crit0, crit1, crit2, crit3, cap, counts, (char *)workspace,
+    return launch_critical(rec, critical_mask, dims, lo, hi, crit0, crit1, crit2, crit3, cap, counts,
+                           (char *)workspace,
                            dev_flags, (hipStream_t)stream);
 }
 
-extern "C" int dms_critical_simplices_noalloc(const uint32_t *rec, const int64_t dims[3], const int64_t lo[3],
+extern "C" int dms_critical_simplices_noalloc(const uint32_t *rec, const uint32_t *critical_mask,
+                                              const int64_t dims[3], const int64_t lo[3],
                                               const int64_t hi[3], int64_t *crit0, int64_t *crit1,
                                               int64_t *crit2, int64_t *crit3, const int64_t cap[4],
                                               int64_t *counts, uint32_t *dev_flags, void *stream)
@@ -717,6 +725,7 @@ extern "C" int dms_critical_simplices_noalloc(const uint32_t *rec, const int64_t
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DMS_E_HIP;
     char *ws = g_scratch[dev].load();
     if (!ws) return DMS_E_NOT_INITIALISED;
-    return launch_critical(rec, dims, lo, hi, crit0, crit1, crit2, crit3, cap, counts, ws, dev_flags,
+    return launch_critical(rec, critical_mask, dims, lo, hi, crit0, crit1, crit2, crit3, cap, counts, ws,
+                           dev_flags,
                            (hipStream_t)stream);
 }

@@ -187,20 +187,21 @@ __device__ __forceinline__ uint32_t low_of_ranks(uint64_t rank_of)
     return low;
 }
 
-__device__ __forceinline__ void robins(uint64_t rank_of, int mmax, const SharedTables &T, uint4 &out);
+__device__ __forceinline__ bool robins(uint64_t rank_of, int mmax, const SharedTables &T, uint4 &out);
 
 // Robins' ProcessLowerStars for one vertex, from the orders of x and its 14
 // neighbours (kAbsent for neighbours outside the grid); mmax as in robins.
+// Returns whether L(x) holds a critical cell.
 template <typename C>
-__device__ __forceinline__ void process_vertex(const C *o, C ox, int mmax, const SharedTables &T,
+__device__ __forceinline__ bool process_vertex(const C *o, C ox, int mmax, const SharedTables &T,
                                                uint4 &out)
 {
     const uint32_t low = lower_mask(o, ox);
     if (low == 0) {  // L(x) = {x}: x is critical
         out = make_uint4(0, 0, 0, 0);
-        return;
+        return true;
     }
-    robins(lower_ranks(o, low), mmax, T, out);
+    return robins(lower_ranks(o, low), mmax, T, out);
 }
 
 // The pairing itself, from the ranks of the lower neighbours (lower_ranks).
@@ -218,13 +219,15 @@ __device__ __forceinline__ void process_vertex(const C *o, C ox, int mmax, const
 // second set critical.  "Smallest" is a bit-sliced minimum over key planes:
 // plane b holds the cells that contain the neighbour of rank b, and the key
 // of a cell is the integer with those bits (Section 2.1 comparison).
-__device__ __forceinline__ void robins(uint64_t rank_of, int mmax, const SharedTables &T, uint4 &out)
+// Returns whether some cell of L(x) ends critical.
+__device__ __forceinline__ bool robins(uint64_t rank_of, int mmax, const SharedTables &T, uint4 &out)
 {
     const uint32_t low = low_of_ranks(rank_of);
     if (low == 0) {
         out = make_uint4(0, 0, 0, 0);
-        return;
+        return true;
     }
+    bool crit = false;
     uint64_t nb_at = 0;  // rank -> neighbour (4 bits each)
 #pragma unroll
     for (int e = 0; e < 14; ++e)
@@ -291,6 +294,7 @@ __device__ __forceinline__ void robins(uint64_t rank_of, int mmax, const SharedT
         }
         // no cell has exactly one unpaired facet: the smallest unpaired edge or
         // cell without unpaired facets is critical
+        crit = true;
         bool edge_wins = fr != 0 && !have_a;
         const int re = fr ? __ffs(fr) - 1 : 31;
         if (fr != 0 && have_a) {
@@ -319,6 +323,7 @@ __device__ __forceinline__ void robins(uint64_t rank_of, int mmax, const SharedT
     }
     out = make_uint4((uint32_t)rec_lo, (uint32_t)(rec_lo >> 32), (uint32_t)rec_hi,
                      (uint32_t)(rec_hi >> 32));
+    return crit;
 }
 
 // ---------------------------------------------------------------------------
@@ -356,18 +361,31 @@ constexpr int kPerm8 = 40320;
 constexpr int kDefect6 = 7 * 64 * kPerm7;
 constexpr int64_t kDefect8 = 7ll * 64 * kPerm8;
 __device__ uint4 g_defect6[kDefect6];
+// One bit per table entry: whether the entry's lower star holds a critical
+// cell (set by the table fillers, read to mark records for the extraction).
+static_assert(kRegular % 64 == 0 && kDefect6 % 64 == 0 && kDefect8 % 64 == 0, "flag words per wave");
+__device__ uint32_t g_regular_flags[kRegular / 32];
+__device__ uint32_t g_defect6_flags[kDefect6 / 32];
+__device__ uint32_t g_defect8_flags[kDefect8 / 32];
 
-// Record of x from one of the tables, or null when x is in none of the
-// families (defect8 may be null: that family then takes the general path).
+// A table lookup: the entry's record (null when x is in no tabulated
+// family), the family's flag bits and the entry index.
+struct TabHit {
+    const uint4 *rec;
+    const uint32_t *flags;
+    uint32_t idx;
+};
+
+// Table entry of x, or a null record when x is in none of the families
+// (defect8 may be null: that family then takes the general path).
 template <typename C>
-__device__ __forceinline__ const uint4 *table_entry(uint32_t low, const C *o,
-                                                    const uint4 *__restrict__ defect8)
+__device__ __forceinline__ TabHit table_entry(uint32_t low, const C *o, const uint4 *__restrict__ defect8)
 {
     const C kHigh = c_highest<C>();
     const uint32_t rev = __brev(low) >> 18;  // bit e -> bit 13 - e
     const uint32_t one = (low ^ rev) & 0x7fu;
     const int npair = __popc(one);
-    if (npair < 6) return nullptr;
+    if (npair < 6) return TabHit{nullptr, nullptr, 0};
     const uint32_t side = __brev((low >> 7) & 0x7fu) >> 25;  // bit i: the lower member is 13 - i
     const uint32_t both = low & rev & 0x7fu;                   // pairs wholly lower
     // slot values without selecting between array elements by a per-lane
@@ -385,7 +403,7 @@ __device__ __forceinline__ const uint4 *table_entry(uint32_t low, const C *o,
         v7 = cmin(v7, w ? a : kHigh);
     }
     const bool eight = both != 0;
-    if (eight && !defect8) return nullptr;
+    if (eight && !defect8) return TabHit{nullptr, nullptr, 0};
     v[7] = v7;
     uint32_t l[8];
 #pragma unroll
@@ -401,12 +419,19 @@ __device__ __forceinline__ const uint4 *table_entry(uint32_t low, const C *o,
     for (int i = 0; i < 7; ++i) code7 += l[i] * f7[i];
 #pragma unroll
     for (int i = 0; i < 8; ++i) code8 += l[i] * f8[i];
-    if (npair == 7) return &g_regular[side * kPerm7 + code7];
+    if (npair == 7) {
+        const uint32_t i = side * kPerm7 + code7;
+        return TabHit{&g_regular[i], g_regular_flags, i};
+    }
     const uint32_t j = (uint32_t)__ffs(~one & 0x7fu) - 1u;
     const uint32_t side6 = (side & ((1u << j) - 1u)) | ((side >> (j + 1u)) << j);
     static_assert(kDefect8 < (1ll << 32), "32-bit index into the wholly-lower table");
-    if (eight) return defect8 + ((j * 64u + side6) * (uint32_t)kPerm8 + code8);
-    return &g_defect6[(j * 64u + side6) * kPerm7 + code7];
+    if (eight) {
+        const uint32_t i = (j * 64u + side6) * (uint32_t)kPerm8 + code8;
+        return TabHit{defect8 + i, g_defect8_flags, i};
+    }
+    const uint32_t i = (j * 64u + side6) * kPerm7 + code7;
+    return TabHit{&g_defect6[i], g_defect6_flags, i};
 }
 
 template <int GX, int GY>
@@ -499,6 +524,12 @@ __device__ __forceinline__ uint32_t size_key(uint32_t low)
     return 1u + (uint32_t)__popc(low) + (uint32_t)__popcll(lower_star_tq(low));
 }
 
+// Marks record r (box index) as holding a critical cell: bit r of the mask.
+__device__ __forceinline__ void mark_critical(uint32_t *mark, int64_t r)
+{
+    atomicOr(&mark[r >> 5], 1u << (uint32_t)(r & 31));
+}
+
 // One GX x GY x 1 tile (1024 vertices) of the owned box [lo, lo + w) of a
 // grid of dims n; record indices are rec_off + position in the owned box.
 // The orders of the tile plus a one-vertex halo are staged in LDS.  Pass 1
@@ -514,7 +545,7 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
                                               int64_t bx, int64_t by, int64_t bz, int64_t rec_off,
                                               uint4 *__restrict__ rec, const uint4 *__restrict__ defect8,
                                               uint4 *__restrict__ queue, uint32_t *qcount, uint32_t qcap,
-                                              uint32_t *flags, BlockShared &sh,
+                                              uint32_t *flags, uint32_t *__restrict__ mark, BlockShared &sh,
                                               typename Keys::H *tile)
 {
     using S = Tile<GX, GY>;
@@ -612,13 +643,15 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
     // overlap instead of adding up
     constexpr int kPer = kTileVerts / kThreads;
     uint32_t gx[kPer], gy[kPer], gz[kPer], gw[kPer];  // the entries, as plain words
+    uint32_t fw[kPer];   // the flag words of the entries
+    uint32_t fbit = 0;   // 5 bits per vertex: the entry's bit in its flag word
     uint32_t state = 0;  // bit k: vertex k in the box; bit kPer + k: it has an entry
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int v = tid + k * kThreads;
         const int tx = GX == kWave ? tid % kWave : v % GX;
         const int ty = GX == kWave ? wave_u + (kThreads / kWave) * k : v / GX;
-        const uint4 *hit = nullptr;
+        TabHit hit{nullptr, g_regular_flags, 0};
         if (bx * GX + tx < w0 && by * GY + ty < w1 && bz < w2) {
             const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
             C o[14], ox;
@@ -626,12 +659,14 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
             hit = table_entry(lower_mask(o, ox), o, defect8);
             state |= 1u << k;
         }
-        if (hit) state |= 1u << (kPer + k);
-        const uint4 e = *(hit ? hit : g_regular);
+        if (hit.rec) state |= 1u << (kPer + k);
+        const uint4 e = *(hit.rec ? hit.rec : g_regular);
         gx[k] = e.x;
         gy[k] = e.y;
         gz[k] = e.z;
         gw[k] = e.w;
+        fw[k] = hit.rec ? hit.flags[hit.idx >> 5] : 0u;
+        fbit |= (hit.idx & 31u) << (5 * k);
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -639,10 +674,13 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
         const int v = tid + k * kThreads;
         const int tx = GX == kWave ? tid % kWave : v % GX;
         const int ty = GX == kWave ? wave_u + (kThreads / kWave) * k : v / GX;
-        if ((state >> (kPer + k)) & 1u)
-            rec[rbase + tx + w0 * ty] = make_uint4(gx[k], gy[k], gz[k], gw[k]);
-        else
+        if ((state >> (kPer + k)) & 1u) {
+            const int64_t r = rbase + tx + w0 * ty;
+            rec[r] = make_uint4(gx[k], gy[k], gz[k], gw[k]);
+            if (mark && ((fw[k] >> ((fbit >> (5 * k)) & 31u)) & 1u)) mark_critical(mark, r);
+        } else {
             sh.list[atomicAdd(&sh.nlist, 1u)] = (uint16_t)v;
+        }
     }
     __syncthreads();
     const uint32_t total = sh.nlist;
@@ -676,8 +714,9 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
         mmax = __builtin_amdgcn_readfirstlane(mmax);
         if (here) {
             uint4 r;
-            robins(rk, mmax, sh.T, r);
+            const bool crit = robins(rk, mmax, sh.T, r);
             rec[ridx] = r;
+            if (mark && crit) mark_critical(mark, ridx);
         }
         return;
     }
@@ -721,8 +760,10 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
         mmax = __builtin_amdgcn_readfirstlane(mmax);
         if (active) {
             uint4 r;
-            process_vertex(o, ox, mmax, sh.T, r);
-            rec[rbase + tx + w0 * ty] = r;
+            const bool crit = process_vertex(o, ox, mmax, sh.T, r);
+            const int64_t ri = rbase + tx + w0 * ty;
+            rec[ri] = r;
+            if (mark && crit) mark_critical(mark, ri);
         }
     }
 }
@@ -738,7 +779,8 @@ __global__ __launch_bounds__(kThreads, 8) void k_gradient(const void *__restrict
                                                        uint4 *__restrict__ rec,
                                                        const uint4 *__restrict__ defect8,
                                                        uint4 *__restrict__ queue, uint32_t *qcount,
-                                                       uint32_t qcap, uint32_t *flags)
+                                                       uint32_t qcap, uint32_t *flags,
+                                                       uint32_t *__restrict__ mark)
 {
     __shared__ BlockShared sh;
     __shared__ typename Keys::H tile[Tile<GX, GY>::kHalo];
@@ -746,7 +788,7 @@ __global__ __launch_bounds__(kThreads, 8) void k_gradient(const void *__restrict
     const int64_t b = blockIdx.x;
     const int64_t bx = b % bx_count, by = (b / bx_count) % by_count, bz = b / (bx_count * by_count);
     gradient_tile<Keys, GX, GY>(field, nx, ny, nz, lo0, lo1, lo2, w0, w1, w2, bx, by, bz, 0, rec, defect8,
-                                queue, qcount, qcap, flags, sh, tile);
+                                queue, qcount, qcap, flags, mark, sh, tile);
 }
 
 // Batched form: many whole fields, concatenated; one block per tile of the
@@ -775,17 +817,25 @@ __global__ __launch_bounds__(kThreads, 8) void k_gradient_batch(const int32_t *_
     const int64_t k = t - tile_start[f];
     const int64_t bx = k % bxc, by = (k / bxc) % byc, bz = k / (bxc * byc);
     gradient_tile<RankKeys, GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1], F.n[2], bx,
-                                    by, bz, F.off, rec, defect8, queue, qcount, qcap, nullptr, sh, tile);
+                                    by, bz, F.off, rec, defect8, queue, qcount, qcap, nullptr, nullptr, sh,
+                                    tile);
 }
 
 __global__ void k_queue_reset(uint32_t *qcount) { *qcount = 0; }
+
+__global__ void k_mark_zero(uint32_t *__restrict__ mark, int64_t words)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < words) mark[i] = 0u;
+}
 
 // Pairs the queued general vertices: block b takes entries
 // [b kQueueChunk, (b+1) kQueueChunk) of the filled part, sorts them by size
 // key and runs Robins' loop on them in full rounds.
 __global__ __launch_bounds__(kThreads) void k_gradient_queue(const uint4 *__restrict__ queue,
                                                              const uint32_t *qcount, uint32_t qcap,
-                                                             uint4 *__restrict__ rec)
+                                                             uint4 *__restrict__ rec,
+                                                             uint32_t *__restrict__ mark)
 {
     __shared__ SharedTables T;
     __shared__ uint32_t bins[kSizeBins];
@@ -818,8 +868,10 @@ __global__ __launch_bounds__(kThreads) void k_gradient_queue(const uint4 *__rest
         mmax = __builtin_amdgcn_readfirstlane(mmax);
         if (active) {
             uint4 r;
-            robins(rk, mmax, T, r);
-            rec[entry_record(e)] = r;
+            const bool crit = robins(rk, mmax, T, r);
+            const int64_t ri = entry_record(e);
+            rec[ri] = r;
+            if (mark && crit) mark_critical(mark, ri);
         }
     }
 }
@@ -855,20 +907,27 @@ __global__ __launch_bounds__(kThreads) void k_regular_table()
     __shared__ SharedTables T;
     load_tables(T);
     __syncthreads();
-    const int idx = blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= kRegular) return;
-    const uint32_t side = idx / kPerm7;
-    uint32_t rank[7];
-    lehmer_decode<7>(idx % kPerm7, rank);
-    int32_t o[14];
-    for (int i = 0; i < 7; ++i) {
-        const int lowm = ((side >> i) & 1u) ? 13 - i : i;
-        o[lowm] = (int32_t)rank[i];
-        o[13 - lowm] = 100 + i;  // above x
+    const int idx = blockIdx.x * kThreads + threadIdx.x;  // a wave covers 64 aligned entries
+    bool crit = false;
+    if (idx < kRegular) {
+        const uint32_t side = idx / kPerm7;
+        uint32_t rank[7];
+        lehmer_decode<7>(idx % kPerm7, rank);
+        int32_t o[14];
+        for (int i = 0; i < 7; ++i) {
+            const int lowm = ((side >> i) & 1u) ? 13 - i : i;
+            o[lowm] = (int32_t)rank[i];
+            o[13 - lowm] = 100 + i;  // above x
+        }
+        uint4 r;
+        crit = process_vertex(o, 50, 14, T, r);
+        g_regular[idx] = r;
     }
-    uint4 r;
-    process_vertex(o, 50, 14, T, r);
-    g_regular[idx] = r;
+    const uint64_t m = __ballot(crit);
+    if (lane_id() == 0 && idx < kRegular) {
+        g_regular_flags[idx / 32] = (uint32_t)m;
+        g_regular_flags[idx / 32 + 1] = (uint32_t)(m >> 32);
+    }
 }
 
 // Fills a one-defect table in the layout table_entry reads: for |L| = 8 the
@@ -883,30 +942,37 @@ __global__ __launch_bounds__(kThreads) void k_defect_table(uint4 *table)
     __syncthreads();
     constexpr int N = kEight ? 8 : 7;
     constexpr int64_t perms = kEight ? kPerm8 : kPerm7;
-    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (idx >= 7 * 64 * perms) return;
-    const uint32_t code = (uint32_t)(idx % perms);
-    const uint32_t js = (uint32_t)(idx / perms);
-    const uint32_t j = js / 64, side6 = js % 64;
-    // the 7-bit side pattern with bit j (pair j) set for both lower
-    const uint32_t side = (side6 & ((1u << j) - 1u)) | ((side6 >> j) << (j + 1u)) |
-                          (kEight ? 1u << j : 0u);
-    uint32_t rank[N];
-    lehmer_decode<N>(code, rank);
-    if (!kEight && rank[j] != 6u) {
-        table[idx] = make_uint4(0, 0, 0, 0);
-        return;
+    constexpr int64_t total = 7 * 64 * perms;
+    uint32_t *flags = kEight ? g_defect8_flags : g_defect6_flags;
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // a wave covers 64 aligned entries
+    bool crit = false;
+    if (idx < total) {
+        const uint32_t code = (uint32_t)(idx % perms);
+        const uint32_t js = (uint32_t)(idx / perms);
+        const uint32_t j = js / 64, side6 = js % 64;
+        // the 7-bit side pattern with bit j (pair j) set for both lower
+        const uint32_t side = (side6 & ((1u << j) - 1u)) | ((side6 >> j) << (j + 1u)) |
+                              (kEight ? 1u << j : 0u);
+        uint32_t rank[N];
+        lehmer_decode<N>(code, rank);
+        uint4 r = make_uint4(0, 0, 0, 0);
+        if (kEight || rank[j] == 6u) {  // other |L| = 6 codes are never read
+            int32_t o[14];
+            for (int e = 0; e < 14; ++e) o[e] = 100 + e;  // above x unless set below
+            for (int i = 0; i < 7; ++i) {
+                if (!kEight && (uint32_t)i == j) continue;
+                o[((side >> i) & 1u) ? 13 - i : i] = (int32_t)rank[i];
+            }
+            if (kEight) o[j] = (int32_t)rank[7];
+            crit = process_vertex(o, 50, 14, T, r);
+        }
+        table[idx] = r;
     }
-    int32_t o[14];
-    for (int e = 0; e < 14; ++e) o[e] = 100 + e;  // above x unless set below
-    for (int i = 0; i < 7; ++i) {
-        if (!kEight && (uint32_t)i == j) continue;
-        o[((side >> i) & 1u) ? 13 - i : i] = (int32_t)rank[i];
+    const uint64_t m = __ballot(crit);
+    if (lane_id() == 0 && idx < total) {
+        flags[idx / 32] = (uint32_t)m;
+        flags[idx / 32 + 1] = (uint32_t)(m >> 32);
     }
-    if (kEight) o[j] = (int32_t)rank[7];
-    uint4 r;
-    process_vertex(o, 50, 14, T, r);
-    table[idx] = r;
 }
 
 }  // namespace
@@ -989,21 +1055,26 @@ static void queue_begin(char *ws, int64_t owned, hipStream_t s, uint4 **queue, u
 }
 
 static void queue_finish(const uint4 *queue, const uint32_t *qcount, uint32_t qcap, uint32_t *rec,
-                         hipStream_t s)
+                         uint32_t *mark, hipStream_t s)
 {
     if (!queue) return;
     const unsigned blocks = (unsigned)((qcap + kQueueChunk - 1) / kQueueChunk);
     hipLaunchKernelGGL(k_gradient_queue, dim3(blocks), dim3(kThreads), 0, s, queue, qcount, qcap,
-                       (uint4 *)rec);
+                       (uint4 *)rec, mark);
 }
 
 template <typename Keys>
 static int launch_gradient_keys(int variant, const void *field, const int64_t *dims, const int64_t *lo,
-                                const int64_t *hi, uint32_t *rec, char *ws, uint32_t *flags,
+                                const int64_t *hi, uint32_t *rec, uint32_t *mark, char *ws, uint32_t *flags,
                                 hipStream_t s)
 {
     const int64_t w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
     if (w0 == 0 || w1 == 0 || w2 == 0) return DMS_OK;
+    if (mark) {
+        const int64_t words = (w0 * w1 * w2 + 31) / 32;
+        hipLaunchKernelGGL(k_mark_zero, dim3((unsigned)((words + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                           mark, words);
+    }
     const int gx = kTileX[variant], gy = kTileVerts / gx;
     const int64_t bxc = (w0 + gx - 1) / gx, byc = (w1 + gy - 1) / gy;
     const int64_t blocks = bxc * byc * w2;
@@ -1015,21 +1086,21 @@ static int launch_gradient_keys(int variant, const void *field, const int64_t *d
 #define DMS_LAUNCH(GXV)                                                                              \
     hipLaunchKernelGGL((k_gradient<Keys, GXV, kTileVerts / GXV>), dim3((unsigned)blocks), dim3(kThreads), \
                        0, s, field, dims[0], dims[1], dims[2], lo[0], lo[1], lo[2], w0, w1, w2, bxc, byc, \
-                       (uint4 *)rec, d8, queue, qcount, qcap, flags)
+                       (uint4 *)rec, d8, queue, qcount, qcap, flags, mark)
     switch (variant) {
     case 0: DMS_LAUNCH(64); break;
     case 1: DMS_LAUNCH(32); break;
     default: DMS_LAUNCH(16); break;
     }
 #undef DMS_LAUNCH
-    queue_finish(queue, qcount, qcap, rec, s);
+    queue_finish(queue, qcount, qcap, rec, mark, s);
     return launch_status();
 }
 
 int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
-                    const int64_t *hi, uint32_t *rec, char *ws, hipStream_t s)
+                    const int64_t *hi, uint32_t *rec, uint32_t *mark, char *ws, hipStream_t s)
 {
-    return launch_gradient_keys<RankKeys>(variant, order, dims, lo, hi, rec, ws, nullptr, s);
+    return launch_gradient_keys<RankKeys>(variant, order, dims, lo, hi, rec, mark, ws, nullptr, s);
 }
 
 int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
@@ -1052,7 +1123,7 @@ int launch_gradient_batch(int variant, const int32_t *order, const BatchField *f
     default: DMS_LAUNCH(16); break;
     }
 #undef DMS_LAUNCH
-    queue_finish(queue, qcount, qcap, rec, s);
+    queue_finish(queue, qcount, qcap, rec, nullptr, s);
     return launch_status();
 }
 
@@ -1067,8 +1138,8 @@ extern "C" size_t dms_gradient_workspace_size(const int64_t dims[3], const int64
 }
 
 extern "C" int dms_discrete_gradient(const int32_t *order, const int64_t dims[3], const int64_t lo[3],
-                                     const int64_t hi[3], uint32_t *rec, void *workspace,
-                                     size_t workspace_bytes, void *stream)
+                                     const int64_t hi[3], uint32_t *rec, uint32_t *critical_mask,
+                                     void *workspace, size_t workspace_bytes, void *stream)
 {
     using namespace dms;
     if (!box_valid(dims, lo, hi)) return DMS_E_ARG;
@@ -1078,12 +1149,12 @@ extern "C" int dms_discrete_gradient(const int32_t *order, const int64_t dims[3]
     if (!order || !rec) return DMS_E_ARG;
     if (workspace && workspace_bytes < gradient_workspace_size(w0 * w1 * w2)) return DMS_E_WORKSPACE;
     if (const int st = tables_ready()) return st;
-    return launch_gradient(0, order, dims, lo, hi, rec, (char *)workspace, (hipStream_t)stream);
+    return launch_gradient(0, order, dims, lo, hi, rec, critical_mask, (char *)workspace, (hipStream_t)stream);
 }
 
 extern "C" int dms_discrete_gradient_values(const void *values, int dtype, const int64_t dims[3],
                                             const int64_t lo[3], const int64_t hi[3], uint32_t *rec,
-                                            void *workspace, size_t workspace_bytes,
+                                            uint32_t *critical_mask, void *workspace, size_t workspace_bytes,
                                             uint32_t *dev_flags, void *stream)
 {
     using namespace dms;
@@ -1096,9 +1167,11 @@ extern "C" int dms_discrete_gradient_values(const void *values, int dtype, const
     if (workspace && workspace_bytes < gradient_workspace_size(w0 * w1 * w2)) return DMS_E_WORKSPACE;
     if (const int st = tables_ready()) return st;
     if (dtype == DMS_F32)
-        return launch_gradient_keys<F32Keys>(0, values, dims, lo, hi, rec, (char *)workspace, dev_flags,
+        return launch_gradient_keys<F32Keys>(0, values, dims, lo, hi, rec, critical_mask, (char *)workspace,
+                                             dev_flags,
                                              (hipStream_t)stream);
-    return launch_gradient_keys<F64Keys>(0, values, dims, lo, hi, rec, (char *)workspace, dev_flags,
+    return launch_gradient_keys<F64Keys>(0, values, dims, lo, hi, rec, critical_mask, (char *)workspace,
+                                         dev_flags,
                                          (hipStream_t)stream);
 }
 

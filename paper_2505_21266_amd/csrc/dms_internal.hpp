@@ -29,8 +29,10 @@ int init_critical_scratch();
 // ws: gradient_workspace_size(owned vertices) bytes for the queue of
 // general vertices, or null (every tile then pairs its own).
 size_t gradient_workspace_size(int64_t owned);
+// mark (may be null): one bit per box record, set for the records that hold
+// a critical cell (zeroed here first).
 int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
-                    const int64_t *hi, uint32_t *rec, char *ws, hipStream_t s);
+                    const int64_t *hi, uint32_t *rec, uint32_t *mark, char *ws, hipStream_t s);
 int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
                           const int64_t *tile_start, const uint16_t *tile_field, int64_t total_tiles,
                           int64_t total_verts, uint32_t *rec, char *ws, hipStream_t s);

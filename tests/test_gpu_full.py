@@ -93,6 +93,23 @@ def _compare_slabs(field, box, rec_gpu, lists_gpu, planes, z_range=None):
     return checked
 
 
+def _check_mask(mask, lists, dims, lo, hi):
+    """The critical mask flags exactly the max vertices of the listed cells
+    (the lists themselves are compared with the oracle's)."""
+    nx, ny, _ = dims
+    w0, w1 = hi[0] - lo[0], hi[1] - lo[1]
+    nbox = w0 * w1 * (hi[2] - lo[2])
+    want = torch.zeros(nbox, dtype=torch.bool, device=mask.device)
+    for lst in lists:
+        v = lst >> 8
+        x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+        want[(x - lo[0]) + w0 * ((y - lo[1]) + w1 * (z - lo[2]))] = True
+    bits = torch.arange(32, device=mask.device, dtype=torch.int32)
+    got = ((mask.view(-1, 1) >> bits) & 1).view(-1).bool()
+    assert not got[nbox:].any()
+    assert torch.equal(got[:nbox], want)
+
+
 # ---------------------------------------------------------------- config 2
 
 def test_config2_exact():
@@ -104,8 +121,10 @@ def test_config2_exact():
     _say("config2: GPU pass")
     vt = _dev(v)
     og = dms.order(vt)
-    rg = dms.discrete_gradient(og, workspace=dms.gradient_workspace(og))
-    lists, counts = dms.critical_simplices(rg, dims)
+    mask = dms.critical_mask(nx * ny * nz, vt.device)
+    rg = dms.discrete_gradient(og, workspace=dms.gradient_workspace(og), mask=mask)
+    lists, counts = dms.critical_simplices(rg, dims, mask=mask)
+    _check_mask(mask, lists, dims, (0, 0, 0), dims)
     del vt
     o = oracle.order(v, nthreads=WORKERS)
     assert np.array_equal(og.cpu().numpy(), o)
@@ -133,8 +152,11 @@ def config3_gpu():
     vt = _dev(v)
     og = dms.order(vt)
     del vt
-    rg = dms.discrete_gradient(og, lo, hi, workspace=dms.gradient_workspace(og, lo, hi))
-    lists, counts = dms.critical_simplices(rg, dims, lo, hi)
+    mask = dms.critical_mask((hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]), og.device)
+    rg = dms.discrete_gradient(og, lo, hi, workspace=dms.gradient_workspace(og, lo, hi), mask=mask)
+    lists, counts = dms.critical_simplices(rg, dims, lo, hi, mask=mask)
+    _check_mask(mask, lists, dims, lo, hi)
+    del mask
     out = dict(v=v, lo=lo, hi=hi, order=og, rec=rg, lists=[l.cpu().numpy() for l in lists],
                counts=counts.cpu().numpy())
     yield out

@@ -426,6 +426,97 @@ def test_critical_lists(dims, kind, seed, box):
         assert c[0] - c[1] + c[2] - c[3] == 1
 
 
+def _mask_bits(mask, nbox):
+    """The first nbox bits of a critical mask (bit r % 32 of word r / 32)."""
+    b = np.unpackbits(mask.cpu().numpy().view(np.uint8), bitorder="little")
+    assert not b[nbox:].any()
+    return b[:nbox].astype(bool)
+
+
+def _records_with_critical(lists, dims, lo, hi):
+    """Box records (box order) that hold a critical cell: the max vertices
+    of the oracle's critical cells."""
+    nx, ny, _ = dims
+    (x0, y0, z0), (x1, y1, z1) = lo, hi
+    w0, w1 = x1 - x0, y1 - y0
+    out = np.zeros(w0 * w1 * (z1 - z0), bool)
+    for lst in lists:
+        v = np.asarray(lst, np.int64) >> 8
+        x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+        out[(x - x0) + w0 * ((y - y0) + w1 * (z - z0))] = True
+    return out
+
+
+MASK_CASES = [(c[0], c[1], c[2], None) for c in GRAD_CASES] + [
+    ((34, 34, 34), "noise", 4, ((1, 1, 1), (33, 33, 33))),
+    ((128, 64, 24), "ramp1.2", 7, None),
+    ((128, 64, 24), "ramp6.0", 9, ((1, 1, 1), (127, 63, 23))),
+    ((45, 37, 29), "f64", 44, ((2, 0, 3), (41, 37, 27))),
+    ((160, 96, 12), "ramp2.5", 45, None),
+]
+
+
+@pytest.mark.parametrize("dims,kind,seed,box", MASK_CASES)
+def test_critical_mask(dims, kind, seed, box):
+    """The gradient's critical mask has exactly the bits of the records that
+    hold a critical cell (from the oracle's lists), on the order path with
+    and without the queue and on the values path; the extraction reading
+    only flagged records gives the oracle's lists and counts."""
+    v = _field(dims, kind, seed)
+    lo, hi = box if box else ((0, 0, 0), dims)
+    o = oracle.order(v)
+    rec, _, _ = oracle.lower_stars(o, dims, lo, hi)
+    want, wcount = oracle.critical_simplices(rec, dims, lo, hi)
+    want_bits = _records_with_critical(want, dims, lo, hi)
+    nbox = want_bits.size
+    _say("critical mask", dims, kind, box)
+    vt, ot = _dev(v), _dev(o)
+    for path in ("order", "order-noqueue", "values"):
+        mask = dms.critical_mask(nbox, vt.device)
+        mask.fill_(-1)  # every word is written by the gradient call
+        if path == "values":
+            grec = dms.discrete_gradient_values(vt, lo, hi, mask=mask)
+        else:
+            grec = dms.discrete_gradient(ot, lo, hi, queue=path == "order", mask=mask)
+        assert (grec.cpu().numpy().view(np.uint32) == rec).all(), path
+        assert np.array_equal(_mask_bits(mask, nbox), want_bits), path
+        lists, counts = dms.critical_simplices(grec, dims, lo, hi, mask=mask)
+        assert (counts.cpu().numpy() == wcount).all(), path
+        for d in range(4):
+            assert np.array_equal(lists[d].cpu().numpy(), want[d]), (path, d)
+
+
+def test_critical_mask_capacity_and_noalloc():
+    """With the mask, truncated lists and the allocation-free extraction
+    still equal the unmasked results."""
+    dims = (40, 40, 40)
+    v = _field(dims, "noise", 22)
+    o = oracle.order(v)
+    rec, _, _ = oracle.lower_stars(o, dims)
+    want, wcount = oracle.critical_simplices(rec, dims)
+    mask = dms.critical_mask(40 ** 3, torch.device("cuda"))
+    grec = dms.discrete_gradient(_dev(o), mask=mask)
+    cap = [max(int(c) // 2, 1) for c in wcount]
+    flags = dms.new_flags(torch.device("cuda"))
+    lists, counts = dms.critical_simplices(grec, dims, cap=cap, flags=flags, mask=mask)
+    assert int(flags.item()) & dms.FLAG_CAPACITY
+    assert (counts.cpu().numpy() == wcount).all()
+    for d in range(4):
+        assert (lists[d].cpu().numpy() == want[d][: cap[d]]).all()
+    full = [int(c) for c in wcount]
+    lists, counts = dms.critical_simplices_noalloc(grec, dims, full, mask=mask)
+    torch.cuda.synchronize()
+    assert (counts.cpu().numpy() == wcount).all()
+    for d in range(4):
+        assert (lists[d].cpu().numpy() == want[d]).all()
+
+
+def test_critical_mask_too_small_is_refused():
+    rec = torch.zeros((65, 4), dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError):
+        dms.critical_simplices(rec, (65, 1, 1), mask=dms.critical_mask(32, rec.device))
+
+
 def test_critical_capacity_flag():
     dims = (40, 40, 40)
     v = _field(dims, "noise", 21)

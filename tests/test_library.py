@@ -73,48 +73,48 @@ def test_argument_errors(L):
     assert L.dms_order_workspace_size(1000, 0) >= 16 * 1000
     assert L.dms_order_workspace_size(1000, 1) >= 24 * 1000
     # gradient
-    assert L.dms_discrete_gradient(None, dp, lp, hp, fake, None, 0, None) == 1
-    assert L.dms_discrete_gradient(fake, dp, lp, badp, fake, None, 0, None) == 1
+    assert L.dms_discrete_gradient(None, dp, lp, hp, fake, None, None, 0, None) == 1
+    assert L.dms_discrete_gradient(fake, dp, lp, badp, fake, None, None, 0, None) == 1
     big, bigp = _a3([2048, 2048, 1024])
-    assert L.dms_discrete_gradient(fake, bigp, lp, hp, fake, None, 0, None) == 2
-    assert L.dms_discrete_gradient(fake, dp, lp, lp, fake, None, 0, None) == 0  # empty box
+    assert L.dms_discrete_gradient(fake, bigp, lp, hp, fake, None, None, 0, None) == 2
+    assert L.dms_discrete_gradient(fake, dp, lp, lp, fake, None, None, 0, None) == 0  # empty box
     neg, negp = _a3([-1, 0, 0])
-    assert L.dms_discrete_gradient(fake, dp, negp, hp, fake, None, 0, None) == 1
+    assert L.dms_discrete_gradient(fake, dp, negp, hp, fake, None, None, 0, None) == 1
     need = L.dms_gradient_workspace_size(dp, lp, hp)
     assert need >= 256 + 16 * 1024
-    assert L.dms_discrete_gradient(fake, dp, lp, hp, fake, fake, need - 1, None) == 3
+    assert L.dms_discrete_gradient(fake, dp, lp, hp, fake, None, fake, need - 1, None) == 3
     assert L.dms_gradient_workspace_size(dp, lp, badp) == 0
     # gradient from the values
-    assert L.dms_discrete_gradient_values(fake, 7, dp, lp, hp, fake, None, 0, fake, None) == 1
-    assert L.dms_discrete_gradient_values(None, 0, dp, lp, hp, fake, None, 0, fake, None) == 1
-    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, None, 0, None, None) == 1
-    assert L.dms_discrete_gradient_values(fake, 1, dp, lp, badp, fake, None, 0, fake, None) == 1
+    assert L.dms_discrete_gradient_values(fake, 7, dp, lp, hp, fake, None, None, 0, fake, None) == 1
+    assert L.dms_discrete_gradient_values(None, 0, dp, lp, hp, fake, None, None, 0, fake, None) == 1
+    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, None, None, 0, None, None) == 1
+    assert L.dms_discrete_gradient_values(fake, 1, dp, lp, badp, fake, None, None, 0, fake, None) == 1
     # no int32 order on this path: grids past 2^31 vertices are accepted, up to 2^40
     huge, hugep = _a3([1 << 21, 1 << 20, 4])
-    assert L.dms_discrete_gradient_values(fake, 0, hugep, lp, hp, fake, None, 0, fake, None) == 2
+    assert L.dms_discrete_gradient_values(fake, 0, hugep, lp, hp, fake, None, None, 0, fake, None) == 2
     assert L.dms_gradient_workspace_size(bigp, lp, hp) > 0
     assert L.dms_gradient_workspace_size(hugep, lp, hp) == 0
-    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, fake, need - 1, fake, None) == 3
-    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, lp, fake, None, 0, fake, None) == 0
+    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, None, fake, need - 1, fake, None) == 3
+    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, lp, fake, None, None, 0, fake, None) == 0
     # critical
     cap, capp = _a3([0, 0, 0, 0])
-    assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, capp, fake, fake, 0,
+    assert L.dms_critical_simplices(fake, None, dp, lp, hp, None, None, None, None, capp, fake, fake, 0,
                                     fake, None) == 3
     ncap, ncapp = _a3([0, -1, 0, 0])
-    assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, ncapp, fake, fake,
+    assert L.dms_critical_simplices(fake, None, dp, lp, hp, None, None, None, None, ncapp, fake, fake,
                                     1 << 20, fake, None) == 1
     c1, c1p = _a3([0, 5, 0, 0])
-    assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, c1p, fake, fake,
+    assert L.dms_critical_simplices(fake, None, dp, lp, hp, None, None, None, None, c1p, fake, fake,
                                     1 << 20, fake, None) == 1
     assert L.dms_critical_workspace_size(dp, lp, badp) == 0
     # allocation-free extraction: same argument checks, and boxes past its
     # scratch array (160 Ki tiles of 1024 records) are refused
-    assert L.dms_critical_simplices_noalloc(fake, dp, lp, hp, None, None, None, None, ncapp, fake, fake,
+    assert L.dms_critical_simplices_noalloc(fake, None, dp, lp, hp, None, None, None, None, ncapp, fake, fake,
                                             None) == 1
-    assert L.dms_critical_simplices_noalloc(fake, dp, lp, hp, None, None, None, None, capp, fake, None,
+    assert L.dms_critical_simplices_noalloc(fake, None, dp, lp, hp, None, None, None, None, capp, fake, None,
                                             None) == 1
     big, bigp = _a3([1024, 1024, 161])
-    assert L.dms_critical_simplices_noalloc(fake, bigp, lp, bigp, None, None, None, None, capp, fake, fake,
+    assert L.dms_critical_simplices_noalloc(fake, None, bigp, lp, bigp, None, None, None, None, capp, fake, fake,
                                             None) == 2
     # backward
     need = L.dms_gradient_backward_workspace_size(3)
@@ -146,16 +146,16 @@ def test_no_device_is_unsupported(L):
     l, lp = _a3([0, 0, 0])
     h, hp = _a3([4, 4, 4])
     assert L.dms_init(None) == 4
-    assert L.dms_discrete_gradient(fake, dp, lp, hp, fake, None, 0, None) == 4
-    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, None, 0, fake, None) == 4
+    assert L.dms_discrete_gradient(fake, dp, lp, hp, fake, None, None, 0, None) == 4
+    assert L.dms_discrete_gradient_values(fake, 0, dp, lp, hp, fake, None, None, 0, fake, None) == 4
     assert L.dms_order(fake, 0, 64, fake, fake, 1 << 30, fake, None) == 4
     cap, capp = _a3([0, 0, 0, 0])
-    assert L.dms_critical_simplices(fake, dp, lp, hp, None, None, None, None, capp, fake, fake, 1 << 20,
+    assert L.dms_critical_simplices(fake, None, dp, lp, hp, None, None, None, None, capp, fake, fake, 1 << 20,
                                     fake, None) == 4
     need = L.dms_gradient_backward_workspace_size(3)
     assert L.dms_gradient_backward(fake, fake, fake, fake, 3, fake, 10, fake, need, None) == 4
     assert L.dms_simplex_values(fake, 0, 10, fake, 3, fake, None) == 4
-    assert L.dms_critical_simplices_noalloc(fake, dp, lp, hp, None, None, None, None, capp, fake, fake,
+    assert L.dms_critical_simplices_noalloc(fake, None, dp, lp, hp, None, None, None, None, capp, fake, fake,
                                             None) == 4
     out = P()
     assert L.dms_batch_create(d.ctypes.data_as(P), 1, 0, 0, None, ctypes.byref(out)) == 4

@@ -68,7 +68,7 @@ def test_noalloc_capacity_and_limit():
     big = np.array([1024, 1024, 161], np.int64)
     zero = np.zeros(3, np.int64)
     capz = np.zeros(4, np.int64)
-    st = L.dms_critical_simplices_noalloc(P(rec.data_ptr()), big.ctypes.data_as(P), zero.ctypes.data_as(P),
+    st = L.dms_critical_simplices_noalloc(P(rec.data_ptr()), None, big.ctypes.data_as(P), zero.ctypes.data_as(P),
                                           big.ctypes.data_as(P), None, None, None, None, capz.ctypes.data_as(P),
                                           P(gcount.data_ptr()), P(flags.data_ptr()), None)
     assert st == 2
