@@ -11,6 +11,8 @@
 //         order, written at tile offset + scan offset as int64 codes
 //         (max vertex id << 8) | local index.  A tile with more than kCand
 //         such records is re-read whole.
+// With the critical mask of the gradient call, count and fill read only the
+// flagged records instead, one wave per tile, and no candidate lists.
 #include <atomic>
 
 #include "dms_common.hpp"
@@ -256,10 +258,7 @@ __device__ __forceinline__ void load_recs(const uint4 *__restrict__ rec, int64_t
 // number per tile (the true number, also beyond kCand).  Records are read
 // striped (record k * kThreads + tid of the tile), so the loads coalesce;
 // the candidates are listed in record order (row k before row k + 1).
-// mask (may be null): bit r set for every record r that holds a critical
-// cell; records with a clear bit count zero cells and are not read.
-__global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec,
-                                                         const uint32_t *__restrict__ mask, int64_t nbox,
+__global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict__ rec, int64_t nbox,
                                                          uint64_t *__restrict__ tile_counts,
                                                          int64_t ntiles, uint16_t *__restrict__ cand,
                                                          uint32_t *__restrict__ ncand)
@@ -272,9 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_crit_count(const uint4 *__restrict
     for (int k = 0; k < kPerThread; ++k) {
         const int64_t r = t0 + k * kThreads + tid;
         uint32_t c[4] = {0, 0, 0, 0};
-        bool take = r < nbox;
-        if (mask && take) take = (mask[r >> 5] >> (uint32_t)(r & 31)) & 1u;
-        if (take) {
+        if (r < nbox) {
             const uint4 w = rec[r];
             count_critical((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), c);
         }
@@ -408,6 +405,188 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill(
     }
     const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
     write_codes<false>(lo, hi, c, at, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+}
+
+// ---------------------------------------------------------------------------
+// Masked extraction: the gradient set bit r of the mask for every record r
+// holding a critical cell, so the other records need not be read.  A wave
+// takes kTilesPerWave consecutive tiles, whose mask words it holds one per
+// lane.  When they flag at most kWave records (the usual case: most
+// vertices hold no critical cell), lane j takes the j-th flagged record and
+// one load serves the whole wave; otherwise the wave walks the tiles in rows
+// of kWave records (row k: words 2k and 2k + 1), skipping empty rows.  The
+// tiles' slots in the scanned counts are consecutive, so one running offset
+// serves both tiles.
+constexpr int kRows = kTileRecs / kWave;
+constexpr int kTileWords = kTileRecs / 32;
+constexpr int kTilesPerWave = kWave / kTileWords;
+constexpr int kWavesPerBlock = kThreads / kWave;
+static_assert(kWave == 64 && kTileWords == 2 * kRows && kTilesPerWave == 2, "one mask word per lane");
+
+// Position of the n-th set bit (n < popc(x)), by halving.
+__device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t n)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t s = 16; s > 0; s >>= 1) {
+        const uint32_t c = (uint32_t)__popc(x & ((1u << s) - 1u));
+        if (n >= c) {
+            n -= c;
+            x >>= s;
+            pos += s;
+        }
+    }
+    return pos;
+}
+
+// The wave's flagged records: word = mask word `lane` of the wave's tiles.
+// Returns their number; when it is at most kWave, rel (of lane j < number)
+// is the j-th flagged record's position from the first tile's start.
+__device__ __forceinline__ uint32_t list_flagged(uint32_t word, int lane, uint32_t &rel)
+{
+    const uint32_t pc = (uint32_t)__popc(word);
+    uint32_t inc = pc;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    const uint32_t total = __shfl(inc, kWave - 1);
+    // the word holding flagged record j = lane: the first w with inc[w] > j
+    const uint32_t j = (uint32_t)lane;
+    int w = 0;
+#pragma unroll
+    for (int step = kWave / 2; step > 0; step >>= 1)
+        if (__shfl(inc, w + step - 1) <= j) w += step;
+    const uint32_t ww = __shfl(word, w);
+    const uint32_t before = __shfl(inc, w) - (uint32_t)__popc(ww);
+    rel = (uint32_t)w * 32u + select_bit(ww, j - before);
+    return total;
+}
+
+// Whether this lane's record of row k is flagged; row_empty when the row
+// flags none.
+__device__ __forceinline__ bool row_bit(uint32_t word, int k, int lane, bool &row_empty)
+{
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)word, 2 * k);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)word, 2 * k + 1);
+    row_empty = (a | b) == 0u;
+    return ((lane < 32 ? a : b) >> (lane & 31)) & 1u;
+}
+
+__device__ __forceinline__ uint64_t count_record(const uint4 *__restrict__ rec, int64_t r, uint64_t &lo,
+                                                 uint64_t &hi)
+{
+    const uint4 w = rec[r];
+    lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
+    hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
+    uint32_t c[4];
+    count_critical(lo, hi, c);
+    return pack4(c);
+}
+
+__global__ __launch_bounds__(kThreads) void k_crit_count_masked(const uint4 *__restrict__ rec,
+                                                                const uint32_t *__restrict__ mask,
+                                                                int64_t nbox,
+                                                                uint64_t *__restrict__ tile_counts,
+                                                                int64_t ntiles)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) tile_counts[4 * ntiles] = 0;
+    const int lane = lane_id();
+    const int64_t tile0 =
+        (int64_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave)) *
+        kTilesPerWave;
+    if (tile0 >= ntiles) return;
+    const int64_t wi = tile0 * kTileWords + lane;
+    const uint32_t word = wi < (nbox + 31) / 32 ? mask[wi] : 0u;
+    const int64_t r0 = tile0 * kTileRecs;
+    uint32_t rel;
+    const uint32_t total = list_flagged(word, lane, rel);
+    uint64_t sum[kTilesPerWave] = {0, 0};
+    uint64_t lo, hi;
+    if (total <= (uint32_t)kWave) {
+        if ((uint32_t)lane < total && r0 + rel < nbox) sum[rel / kTileRecs] = count_record(rec, r0 + rel, lo, hi);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kTilesPerWave * kRows; ++k) {
+            bool empty;
+            const bool flagged = row_bit(word, k, lane, empty);
+            if (empty) continue;
+            const int64_t r = r0 + k * kWave + lane;
+            if (flagged && r < nbox) sum[k / kRows] += count_record(rec, r, lo, hi);
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        sum[0] += __shfl_xor(sum[0], off);
+        sum[1] += __shfl_xor(sum[1], off);
+    }
+#pragma unroll
+    for (int t = 0; t < kTilesPerWave; ++t)
+        if (lane < 4 && tile0 + t < ntiles) tile_counts[(int64_t)lane * ntiles + tile0 + t] = lane16(sum[t], lane);
+}
+
+__global__ __launch_bounds__(kThreads) void k_crit_fill_masked(
+    const uint4 *__restrict__ rec, const uint32_t *__restrict__ mask, int64_t nbox,
+    const uint64_t *__restrict__ offs, int64_t ntiles, int64_t w0, int64_t w1, int64_t lo0, int64_t lo1,
+    int64_t lo2, int64_t nx, int64_t ny, int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3,
+    int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
+{
+    __shared__ EdgeTris E;
+    load_edge_tris(E);
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t tile0 =
+        (int64_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave)) *
+        kTilesPerWave;
+    if (tile0 >= ntiles) return;
+    const int64_t wi = tile0 * kTileWords + lane;
+    const uint32_t word = wi < (nbox + 31) / 32 ? mask[wi] : 0u;
+    if (!__ballot(word != 0u)) return;
+    uint64_t at[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) at[d] = offs[(int64_t)d * ntiles + tile0] - offs[(int64_t)d * ntiles];
+    const int64_t r0 = tile0 * kTileRecs;
+    uint32_t rel;
+    const uint32_t total = list_flagged(word, lane, rel);
+    const bool listed = total <= (uint32_t)kWave;
+#pragma unroll 1
+    for (int k = 0; k < (listed ? 1 : kTilesPerWave * kRows); ++k) {
+        int64_t r;
+        bool take;
+        if (listed) {
+            r = r0 + rel;
+            take = (uint32_t)lane < total;
+        } else {
+            bool empty;
+            take = row_bit(word, k, lane, empty);
+            if (empty) continue;
+            r = r0 + k * kWave + lane;
+        }
+        uint64_t lo = 0, hi = 0, pk = 0;
+        if (take && r < nbox) pk = count_record(rec, r, lo, hi);
+        uint64_t inc = pk;  // inclusive scan of the packed counts over the wave
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint64_t t = __shfl_up(inc, off);
+            if (lane >= off) inc += t;
+        }
+        const uint64_t tot = __shfl(inc, kWave - 1);
+        if (pk != 0) {
+            const uint64_t ex = inc - pk;
+            uint64_t a[4];
+            uint32_t c[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                a[d] = at[d] + lane16(ex, d);
+                c[d] = lane16(pk, d);
+            }
+            const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
+            write_codes<false>(lo, hi, c, a, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) at[d] += lane16(tot, d);
+    }
 }
 
 __global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *counts, int64_t cap0,
@@ -610,12 +789,23 @@ int launch_critical(const uint32_t *rec, const uint32_t *mask, const int64_t *di
         hipLaunchKernelGGL(k_crit_empty, dim3(1), dim3(64), 0, s, counts);
         return launch_status();
     }
-    hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       mask, nbox, tc, ntiles, cand, ncand);
-    exclusive_scan<uint64_t>(tc, len, partials, s);
-    hipLaunchKernelGGL(k_crit_fill, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       nbox, tc, ntiles, cand, ncand, w0, w1, lo[0], lo[1], lo[2], dims[0], dims[1],
-                       crit0, crit1, crit2, crit3, cap[0], cap[1], cap[2], cap[3]);
+    if (mask) {
+        const int64_t per_block = (int64_t)kWavesPerBlock * kTilesPerWave;
+        const unsigned blocks = (unsigned)((ntiles + per_block - 1) / per_block);
+        hipLaunchKernelGGL(k_crit_count_masked, dim3(blocks), dim3(kThreads), 0, s, (const uint4 *)rec, mask,
+                           nbox, tc, ntiles);
+        exclusive_scan<uint64_t>(tc, len, partials, s);
+        hipLaunchKernelGGL(k_crit_fill_masked, dim3(blocks), dim3(kThreads), 0, s, (const uint4 *)rec, mask,
+                           nbox, tc, ntiles, w0, w1, lo[0], lo[1], lo[2], dims[0], dims[1], crit0, crit1,
+                           crit2, crit3, cap[0], cap[1], cap[2], cap[3]);
+    } else {
+        hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
+                           nbox, tc, ntiles, cand, ncand);
+        exclusive_scan<uint64_t>(tc, len, partials, s);
+        hipLaunchKernelGGL(k_crit_fill, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
+                           nbox, tc, ntiles, cand, ncand, w0, w1, lo[0], lo[1], lo[2], dims[0], dims[1],
+                           crit0, crit1, crit2, crit3, cap[0], cap[1], cap[2], cap[3]);
+    }
     hipLaunchKernelGGL(k_crit_finish, dim3(1), dim3(64), 0, s, tc, ntiles, counts, cap[0], cap[1],
                        cap[2], cap[3], dev_flags);
     return launch_status();
@@ -657,7 +847,7 @@ int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, i
     uint16_t *cand = (uint16_t *)(ws + L.cand);
     uint32_t *ncand = (uint32_t *)(ws + L.ncand);
     hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       (const uint32_t *)nullptr, n, tc, ntiles, cand, ncand);
+                       n, tc, ntiles, cand, ncand);
     exclusive_scan<uint64_t>(tc, len, partials, s);
     hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
                        (const uint4 *)rec, n, tc, ntiles, cand, ncand, foff, nfields, crit[0], crit[1],
