@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--large", action="store_true",
                     help="time the order-free path (gradient from the values + extraction) on the "
                          "2048x1920x1536 float32 field instead (one JSON line of its own)")
+    ap.add_argument("--only", choices=["batched", "differentiable"], default=None,
+                    help="run only the batched (96-field) or the differentiable (128^3 f64) part and "
+                         "print its object as the JSON line (for profiling)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -322,6 +325,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.large:
         bench_large(args, dev)
+        return
+    if args.only == "batched":
+        print(json.dumps(bench_batched(dev, max(args.steps, 3))), flush=True)
+        return
+    if args.only == "differentiable":
+        print(json.dumps(bench_differentiable(dev, max(args.steps, 3))), flush=True)
         return
     if args.copy_mib:
         src = torch.ones(args.copy_mib * (1 << 18), dtype=torch.int32, device=dev)

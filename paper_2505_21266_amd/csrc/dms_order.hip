@@ -40,8 +40,6 @@ constexpr int kRadix = 256;
 // 8-byte keys keep 256 threads: two 512-thread blocks of those would not fit
 // one CU's LDS and registers.  The fine partition of the inversion keeps 256.
 constexpr int kWideThreads = 512;
-template <typename K>
-constexpr int pass_threads() { return sizeof(K) == 4 ? kWideThreads : kThreads; }
 
 // Key types: uint32_t for float32, uint64_t for float64 and for batches
 // (field index from bit 32 up, above the float32 key): a batch sorts the four
@@ -234,6 +232,14 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
     }
 }
 
+// Key storage between passes.  Every pass sorts by one byte of the stored
+// key.  Except for batches of more than kFieldPassFields fields (whose last
+// pass reads the field from the top of the 64-bit key), a pass writes the
+// key without the byte it consumed, in the narrowest type that holds the
+// rest, so that later passes read and write fewer bytes; the digit is then
+// always the stored key's low byte.  NoKey: nothing left to store.
+struct NoKey {};
+
 // Rank of an item among the wave's items with the same 8-bit digit, counting
 // this k and all earlier ones; wh is the wave's row of counts.  Items of a
 // wave are in element order (k major, lane minor), so ranks are stable.
@@ -307,11 +313,13 @@ __device__ __forceinline__ void zero_masks(Staging<A, B, kThr> &S)
     for (int i = threadIdx.x; i < (kThr / kWave) * kRadix; i += kThr) (&S.mk[0][0])[i] = 0ull;
 }
 
-template <typename V, typename K, bool kFirst, int kThr>
+// KD: the type the keys are written in, (KD)(key >> strip); NoKey when the
+// next pass reads no key.
+template <typename V, typename K, typename KD, bool kFirst, int kThr>
 __global__ __launch_bounds__(kThr) void k_scatter(const void *src, const uint32_t *src_ids,
-                                                      int64_t n, int shift,
+                                                      int64_t n, int shift, int strip,
                                                       const uint32_t *offsets, int64_t ntiles,
-                                                      K *dst_keys, uint32_t *dst_ids,
+                                                      void *dst_keys, uint32_t *dst_ids,
                                                       const int64_t *foff, int nfields)
 {
     constexpr int kW = kThr / kWave;
@@ -396,7 +404,7 @@ __global__ __launch_bounds__(kThr) void k_scatter(const void *src, const uint32_
             const uint32_t g = gbase[(uint32_t)(kk >> shift) & (kRadix - 1)] + (uint32_t)p;
             // the ranks make g < n; the guard keeps any breach of that in bounds
             if ((int64_t)g < n) {
-                dst_keys[g] = kk;
+                if constexpr (!std::is_same_v<KD, NoKey>) ((KD *)dst_keys)[g] = (KD)(kk >> strip);
                 dst_ids[g] = S.st.b[p];
             }
         }
@@ -736,8 +744,75 @@ OrderLayout order_layout(int64_t n)
     return L;
 }
 
+// Bytes of the stored key when `bits` bits of it remain (0: none left).
+constexpr int key_bytes(int bits) { return bits <= 0 ? 0 : bits <= 8 ? 1 : bits <= 16 ? 2 : bits <= 32 ? 4 : 8; }
+
+// One radix pass other than the last (histogram, scan, scatter).
+struct PassArgs {
+    const void *src;
+    const uint32_t *sids;
+    int64_t n;
+    int shift, strip;
+    uint32_t *counts, *partials, *flags;
+    void *dkeys;
+    uint32_t *dids;
+    const int64_t *foff;
+    int nfields;
+    hipStream_t s;
+};
+
+// Blocks of 512 threads (8192-key tiles) for keys up to 4 bytes, 256 for
+// 8-byte keys (two 512-thread blocks of those would not fit one CU's LDS).
+template <typename K>
+constexpr int pass_threads() { return sizeof(K) == 8 ? kThreads : kWideThreads; }
+
+template <typename V, typename K, typename KD, bool kFirst>
+void radix_pass(const PassArgs &A)
+{
+    constexpr int kW = pass_threads<K>();
+    const int64_t nt = (A.n + kW * kItems - 1) / (kW * kItems);
+    hipLaunchKernelGGL((k_tile_hist<V, K, kFirst, kW>), dim3((unsigned)nt), dim3(kW), 0, A.s, A.src, A.n,
+                       A.shift, A.counts, nt, A.flags, nullptr, 0, nullptr, nullptr, 0);
+    exclusive_scan<uint32_t>(A.counts, nt * kRadix, A.partials, A.s);
+    hipLaunchKernelGGL((k_scatter<V, K, KD, kFirst, kW>), dim3((unsigned)nt), dim3(kW), 0, A.s, A.src, A.sids,
+                       A.n, A.shift, A.strip, A.counts, nt, A.dkeys, A.dids, A.foff, A.nfields);
+}
+
+// A middle pass by the stored key's bytes before (ks) and after (kd) it.
+int radix_mid_pass(int ks, int kd, const PassArgs &A)
+{
+    switch (ks * 16 + kd) {
+    case 8 * 16 + 8: radix_pass<uint64_t, uint64_t, uint64_t, false>(A); return DMS_OK;
+    case 8 * 16 + 4: radix_pass<uint64_t, uint64_t, uint32_t, false>(A); return DMS_OK;
+    case 4 * 16 + 4: radix_pass<uint32_t, uint32_t, uint32_t, false>(A); return DMS_OK;
+    case 4 * 16 + 2: radix_pass<uint32_t, uint32_t, uint16_t, false>(A); return DMS_OK;
+    case 2 * 16 + 1: radix_pass<uint16_t, uint16_t, uint8_t, false>(A); return DMS_OK;
+    case 1 * 16 + 0: radix_pass<uint8_t, uint8_t, NoKey, false>(A); return DMS_OK;
+    default: return DMS_E_ARG;
+    }
+}
+
+// The last pass (histograms of the digit and of the id buckets, scans,
+// level-0 scatter of the (id, position) pairs) on stored keys KS.
+template <typename KS, bool kField>
+void last_pass(const void *src, const uint32_t *sids, int64_t n, int shift, const InvertPlan &P,
+               uint32_t *counts, uint32_t *partials, uint32_t *bcounts, uint32_t *bpartials, uint32_t *flags,
+               const int64_t *foff, int nfields, uint32_t *aid, int32_t *apos, hipStream_t s)
+{
+    constexpr int kW = pass_threads<KS>();
+    const int64_t nt = (n + kW * kItems - 1) / (kW * kItems);
+    hipLaunchKernelGGL((k_tile_hist<KS, KS, false, kW, kField>), dim3((unsigned)nt), dim3(kW), 0, s, src, n,
+                       shift, counts, nt, flags, sids, P.bshift, bcounts, foff, nfields);
+    exclusive_scan<uint32_t>(counts, nt * kRadix, partials, s);
+    exclusive_scan<uint32_t>(bcounts, nt * kRadix, bpartials, s);
+    hipLaunchKernelGGL((k_scatter_last<KS, kW, kField>), dim3((unsigned)nt), dim3(kW), 0, s, (const KS *)src,
+                       sids, n, shift, counts, bcounts, nt, foff, nfields, P.bshift, aid, apos);
+}
+
 // field_last: a batch of at most kFieldPassFields fields with 4-byte keys;
 // passes - 1 value passes, then the last pass orders by the field of each id.
+// Keys are stored stripped of consumed bytes (NoKey) except for batches
+// with 64-bit keys.
 template <typename V, typename K>
 int run_order(const void *values, int64_t n, int passes, int32_t *order, char *ws, uint32_t *flags,
               const int64_t *foff, int nfields, hipStream_t s, bool field_last = false)
@@ -746,64 +821,55 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
     if (field_last && (sizeof(K) != 4 || !foff || nfields > kFieldPassFields)) return DMS_E_ARG;
     const OrderLayout L = order_layout<K>(n);
     const InvertPlan P = invert_plan(n);
-    const int64_t ntiles = (n + kTile - 1) / kTile;
-    constexpr int kWide = pass_threads<K>();
-    const int64_t nwide = (n + kWide * kItems - 1) / (kWide * kItems);
-    K *keys[2] = {(K *)(ws + L.keys0), (K *)(ws + L.keys1)};
+    const bool strip = !(sizeof(K) == 8 && foff);
+    const int key_bits = field_last ? 32 : 8 * passes;
+    char *keys[2] = {ws + L.keys0, ws + L.keys1};
     uint32_t *ids[2] = {(uint32_t *)(ws + L.ids0), (uint32_t *)(ws + L.ids1)};
     uint32_t *counts = (uint32_t *)(ws + L.counts);
     uint32_t *partials = (uint32_t *)(ws + L.partials);
     uint32_t *bcounts = (uint32_t *)(ws + L.bcounts);
     uint32_t *bpartials = (uint32_t *)(ws + L.bpartials);
-    const dim3 block(kThreads);
-    const dim3 wgrid((unsigned)nwide), wblock(kWide);
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
+        // digits: the stored key's low byte, or byte p of the whole key
+        const int shift = strip ? 0 : 8 * p;
         const bool last = p == passes - 1;
         const void *src = p == 0 ? values : (const void *)keys[(p - 1) & 1];
         const uint32_t *sids = p == 0 ? nullptr : ids[(p - 1) & 1];
         if (!last) {
+            PassArgs A{src, sids, n, shift, strip ? 8 : 0, counts, partials, flags, keys[p & 1], ids[p & 1],
+                       foff, nfields, s};
             if (p == 0) {
-                hipLaunchKernelGGL((k_tile_hist<V, K, true, kWide>), wgrid, wblock, 0, s, src, n, shift,
-                                   counts, nwide, flags, nullptr, 0, nullptr, nullptr, 0);
-                exclusive_scan<uint32_t>(counts, nwide * kRadix, partials, s);
-                hipLaunchKernelGGL((k_scatter<V, K, true, kWide>), wgrid, wblock, 0, s, src, sids, n, shift,
-                                   counts, nwide, keys[p & 1], ids[p & 1], foff, nfields);
+                // the first pass writes K: at least 24 bits of a 32-bit key and 56 of a 64-bit one remain
+                if (strip && key_bytes(key_bits - 8) != (int)sizeof(K)) return DMS_E_ARG;
+                radix_pass<V, K, K, true>(A);
             } else {
-                hipLaunchKernelGGL((k_tile_hist<V, K, false, kWide>), wgrid, wblock, 0, s, src, n, shift,
-                                   counts, nwide, flags, nullptr, 0, nullptr, nullptr, 0);
-                exclusive_scan<uint32_t>(counts, nwide * kRadix, partials, s);
-                hipLaunchKernelGGL((k_scatter<V, K, false, kWide>), wgrid, wblock, 0, s, src, sids, n,
-                                   shift, counts, nwide, keys[p & 1], ids[p & 1], foff, nfields);
+                const int ks = strip ? key_bytes(key_bits - 8 * p) : (int)sizeof(K);
+                const int kd = strip ? key_bytes(key_bits - 8 * (p + 1)) : (int)sizeof(K);
+                if (const int st = radix_mid_pass(ks, kd, A)) return st;
             }
             continue;
         }
-        if (field_last)
-            hipLaunchKernelGGL((k_tile_hist<V, K, false, kWide, true>), wgrid, wblock, 0, s, src, n, shift,
-                               counts, nwide, flags, sids, P.bshift, bcounts, foff, nfields);
-        else
-            hipLaunchKernelGGL((k_tile_hist<V, K, false, kWide>), wgrid, wblock, 0, s, src, n, shift, counts,
-                               nwide, flags, sids, P.bshift, bcounts, nullptr, 0);
-        exclusive_scan<uint32_t>(counts, nwide * kRadix, partials, s);
-        exclusive_scan<uint32_t>(bcounts, nwide * kRadix, bpartials, s);
         // level 0 into the free buffers; level 1 back into the last pass's
         // source buffers once they are read
         uint32_t *aid = (uint32_t *)keys[p & 1];
         int32_t *apos = (int32_t *)ids[p & 1];
         if (field_last)
-            hipLaunchKernelGGL((k_scatter_last<K, kWide, true>), wgrid, wblock, 0, s, (const K *)src, sids, n,
-                               shift, counts, bcounts, nwide, foff, nfields, P.bshift, aid, apos);
+            last_pass<uint32_t, true>(src, sids, n, 0, P, counts, partials, bcounts, bpartials, flags, foff,
+                                      nfields, aid, apos, s);
+        else if (strip)
+            last_pass<uint8_t, false>(src, sids, n, 0, P, counts, partials, bcounts, bpartials, flags, foff,
+                                      nfields, aid, apos, s);
         else
-            hipLaunchKernelGGL((k_scatter_last<K, kWide>), wgrid, wblock, 0, s, (const K *)src, sids, n, shift,
-                               counts, bcounts, nwide, foff, nfields, P.bshift, aid, apos);
+            last_pass<uint64_t, false>(src, sids, n, shift, P, counts, partials, bcounts, bpartials, flags,
+                                       foff, nfields, aid, apos, s);
         if (P.fine) {
             uint32_t *fid = (uint32_t *)keys[(p - 1) & 1];
             int32_t *fpos = (int32_t *)ids[(p - 1) & 1];
             const dim3 cgrid((unsigned)P.nchunks);
-            hipLaunchKernelGGL(k_fine_hist, cgrid, block, 0, s, aid, n, P.fshift, P.flog, P.qlog,
+            hipLaunchKernelGGL(k_fine_hist, cgrid, dim3(kThreads), 0, s, aid, n, P.fshift, P.flog, P.qlog,
                                P.nchunks, counts);
             exclusive_scan<uint32_t>(counts, P.nchunks << P.flog, partials, s);
-            hipLaunchKernelGGL(k_fine_scatter, cgrid, block, 0, s, aid, apos, n, P.fshift, P.flog,
+            hipLaunchKernelGGL(k_fine_scatter, cgrid, dim3(kThreads), 0, s, aid, apos, n, P.fshift, P.flog,
                                P.qlog, P.nchunks, counts, fid, fpos);
             aid = fid;
             apos = fpos;
