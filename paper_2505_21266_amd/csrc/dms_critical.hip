@@ -54,24 +54,6 @@ __device__ __forceinline__ uint32_t lower_edges(uint64_t lo)
     return (uint32_t)x;
 }
 
-__device__ __forceinline__ uint64_t lower_tris(uint32_t low)
-{
-    uint64_t out = 0;
-#pragma unroll
-    for (int e = 0; e < 14; ++e)
-        if (!((low >> e) & 1u)) out |= kTables.edge_trimask[e];
-    return ~out & ((1ull << 36) - 1);
-}
-
-__device__ __forceinline__ uint32_t lower_tets(uint32_t low)
-{
-    uint32_t out = 0;
-#pragma unroll
-    for (int e = 0; e < 14; ++e)
-        if (!((low >> e) & 1u)) out |= kTables.edge_tetmask[e];
-    return ~out & ((1u << 24) - 1);
-}
-
 // Number of star triangles (low byte) and tets (high byte) in L(x) for each
 // 14-bit lower-neighbour mask: the cells all of whose other vertices are
 // lower neighbours.
@@ -143,10 +125,62 @@ __device__ __forceinline__ int64_t box_vertex(int64_t r, int64_t w0, int64_t w1,
     return i + nx * (j + ny * k);
 }
 
-// Star triangles of each edge (edge_tris), staged in LDS by the fill
-// kernels so that an edge field 3 + j names its head triangle with one read.
+// Star triangles (bits 0..35) and star tets (bits 36..59) of L(x) for each
+// 14-bit lower-neighbour mask: the cells all of whose edges are lower.
+// Built like CellCounts: adding the highest lower neighbour e adds the
+// triangles and tets through e whose other edges are already lower.
+struct LowerCells {
+    uint64_t m[1 << 14];
+};
+
+constexpr LowerCells make_lower_cells()
+{
+    LowerCells L{};
+    const Tables &T = kTables;
+    // per edge e: its star triangles and tets, each with the mask of its
+    // other edges
+    int n[14] = {};
+    uint8_t bit[14][12] = {};
+    uint16_t other[14][12] = {};
+    for (int t = 0; t < 36; ++t)
+        for (int c = 0; c < 2; ++c) {
+            const int e = T.tri[t][c];
+            bit[e][n[e]] = (uint8_t)t;
+            other[e][n[e]++] = (uint16_t)(1u << T.tri[t][1 - c]);
+        }
+    for (int q = 0; q < 24; ++q)
+        for (int c = 0; c < 3; ++c) {
+            const int e = T.tet[q][c];
+            uint16_t m = 0;
+            for (int d = 0; d < 3; ++d)
+                if (d != c) m = (uint16_t)(m | (1u << T.tet[q][d]));
+            bit[e][n[e]] = (uint8_t)(36 + q);
+            other[e][n[e]++] = m;
+        }
+    L.m[0] = 0;
+    for (uint32_t low = 1; low < (1u << 14); ++low) {
+        int e = 13;
+        while (!((low >> e) & 1u)) --e;
+        const uint32_t rest = low & ~(1u << e);
+        uint64_t m = L.m[rest];
+        for (int k = 0; k < n[e]; ++k)
+            if ((other[e][k] & rest) == other[e][k]) m |= 1ull << bit[e][k];
+        L.m[low] = m;
+    }
+    return L;
+}
+
+constexpr LowerCells kLowerCells = make_lower_cells();
+static_assert(kLowerCells.m[(1u << 14) - 1] == (1ull << 60) - 1 && kLowerCells.m[1u << 13] == 0,
+              "all 60 cells when every neighbour is lower, none for a single edge");
+__device__ const LowerCells g_lower_cells = kLowerCells;
+
+// Star triangles of each edge (edge_tris) and star tets of each triangle
+// (tri_tets), staged in LDS by the fill kernels so that a field names its
+// partner with one read.
 struct EdgeTris {
     uint8_t t[14][8];
+    uint8_t q[36][2];
 };
 
 __device__ __forceinline__ void load_edge_tris(EdgeTris &E)
@@ -155,62 +189,68 @@ __device__ __forceinline__ void load_edge_tris(EdgeTris &E)
     if (i < 14 * 8) {
         const int e = i / 8, j = i % 8;
         E.t[e][j] = (uint8_t)(j < kTables.edge_ntri[e] ? kTables.edge_tris[e][j] : 0);
+    } else if (i < 14 * 8 + 36 * 2) {
+        const int k = i - 14 * 8;
+        E.q[k / 2][k % 2] = (uint8_t)kTables.tri_tets[k / 2][k % 2];
     }
 }
 
 // Writes the critical cells of one record (counts c, first slots at) as
-// codes base | local index.
-// kConstBits: the head tet of a triangle comes from a per-lane choice
-// between two constant bits instead of between two table entries, which the
-// compiler turns into a load it waits for.  Measured per kernel: the batched
-// fill (dense tiles of noise fields) gains, while the single-field fill
-// keeps the table form, whose lower register count keeps more of its
-// mostly one-wave candidate blocks resident.
-template <bool kConstBits>
-__device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint32_t *c,
-                                            const uint64_t *at, int64_t base, const EdgeTris &E,
-                                            int64_t *crit0, int64_t *crit1, int64_t *crit2,
-                                            int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2,
-                                            int64_t cap3)
+// codes base | local index.  Only the fields that name a partner are
+// visited (bit tricks on the nibbles and 2-bit fields), and the cells of
+// L(x) come from one table read.
+__device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint32_t *c, const uint64_t *at,
+                                            int64_t base, const EdgeTris &E, int64_t *crit0, int64_t *crit1,
+                                            int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
+                                            int64_t cap2, int64_t cap3)
 {
     if (c[0]) {
         if ((int64_t)at[0] < cap0) crit0[at[0]] = base;
         return;  // a minimum has an empty lower star beyond itself
     }
-    const uint32_t low = lower_edges(lo);
-    uint32_t crit_e = 0;
-    uint64_t head_t = 0, tail_t = 0;
+    const uint64_t ef = lo & kNib14;
+    const uint64_t cells = g_lower_cells.m[lower_edges(lo)];
+    // edge fields equal to 2 (critical edges): bit 4e
+    const uint64_t y = ef ^ 0x0022222222222222ull;
+    uint64_t me = ~(y | (y >> 1) | (y >> 2) | (y >> 3)) & 0x0011111111111111ull;
+    // edge fields >= 3 (paired with triangle field - 3 of the edge): bit 4e + 3
+    uint64_t mh = (ef + 0x0055555555555555ull) & 0x0088888888888888ull;
+    uint64_t head_t = 0;
+    while (mh) {
+        const int b = __ffsll((unsigned long long)mh) - 1;
+        mh &= mh - 1;
+        const int e = b >> 2;
+        head_t |= 1ull << E.t[e][((uint32_t)(ef >> (4 * e)) & 15u) - 3u];
+    }
+    // non-zero triangle fields (paired with star tet field - 1 of the triangle)
+    uint64_t tail_t = 0;
     uint32_t head_q = 0;
-#pragma unroll
-    for (int e = 0; e < 14; ++e) {
-        const uint32_t f = edge_field(lo, e);
-        if (f == 2) crit_e |= 1u << e;
-        if (f >= 3) head_t |= 1ull << E.t[e][(f - 3) & 7];
+    const uint64_t f0 = lo >> 56, f1 = hi;
+    uint64_t n0 = (f0 | (f0 >> 1)) & 0x55ull;
+    uint64_t n1 = (f1 | (f1 >> 1)) & 0x5555555555555555ull;
+    while (n0) {
+        const int b = __ffsll((unsigned long long)n0) - 1;
+        n0 &= n0 - 1;
+        const int t = b >> 1;
+        tail_t |= 1ull << t;
+        head_q |= 1u << E.q[t][((uint32_t)(f0 >> b) & 3u) - 1u];
     }
-#pragma unroll
-    for (int t = 0; t < 36; ++t) {
-        const uint32_t g = tri_field(lo, hi, t);
-        if (g) {
-            tail_t |= 1ull << t;
-            if constexpr (kConstBits) {
-                const uint32_t q0 = 1u << kTables.tri_tets[t][0], q1 = 1u << kTables.tri_tets[t][1];
-                head_q |= g == 1 ? q0 : q1;
-            } else {
-                head_q |= 1u << (g == 1 ? kTables.tri_tets[t][0] : kTables.tri_tets[t][1]);
-            }
-        }
+    while (n1) {
+        const int b = __ffsll((unsigned long long)n1) - 1;
+        n1 &= n1 - 1;
+        const int t = 4 + (b >> 1);
+        tail_t |= 1ull << t;
+        head_q |= 1u << E.q[t][((uint32_t)(f1 >> b) & 3u) - 1u];
     }
-    const uint64_t crit_t = lower_tris(low) & ~head_t & ~tail_t;
-    const uint32_t crit_q = lower_tets(low) & ~head_q;
-    uint32_t m = crit_e;
+    uint64_t mt = cells & ((1ull << 36) - 1) & ~head_t & ~tail_t;
+    uint32_t mq = (uint32_t)(cells >> 36) & ~head_q;
     int64_t a = (int64_t)at[1];
-    while (m) {
-        const int e = __ffs(m) - 1;
-        m &= m - 1;
+    while (me) {
+        const int e = (__ffsll((unsigned long long)me) - 1) >> 2;
+        me &= me - 1;
         if (a < cap1) crit1[a] = base | e;
         ++a;
     }
-    uint64_t mt = crit_t;
     a = (int64_t)at[2];
     while (mt) {
         const int t = __ffsll((unsigned long long)mt) - 1;
@@ -218,7 +258,6 @@ __device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint
         if (a < cap2) crit2[a] = base | t;
         ++a;
     }
-    uint32_t mq = crit_q;
     a = (int64_t)at[3];
     while (mq) {
         const int q = __ffs(mq) - 1;
@@ -347,7 +386,7 @@ __device__ __forceinline__ void fill_tile_full(
 #pragma unroll
         for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
         const int64_t v = box_vertex(r0 + k, w0, w1, lo0, lo1, lo2, nx, ny);
-        write_codes<false>(lo[k], hi[k], c, at[k], v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2,
+        write_codes(lo[k], hi[k], c, at[k], v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2,
                            cap3);
     }
 }
@@ -404,7 +443,7 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill(
         c[d] = lane16(pk, d);
     }
     const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
-    write_codes<false>(lo, hi, c, at, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+    write_codes(lo, hi, c, at, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 }
 
 // ---------------------------------------------------------------------------
@@ -582,7 +621,7 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_masked(
                 c[d] = lane16(pk, d);
             }
             const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
-            write_codes<false>(lo, hi, c, a, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+            write_codes(lo, hi, c, a, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
         }
 #pragma unroll
         for (int d = 0; d < 4; ++d) at[d] += lane16(tot, d);
@@ -616,73 +655,78 @@ __device__ __forceinline__ int record_field(const int64_t *so, int nfields, int6
 }
 
 // Batched fill: records of whole fields concatenated; codes carry the
-// field-local vertex id.  As k_crit_fill: a tile with no listed records is
-// skipped, one with at most kCand is served by one wave, a fuller one is
-// re-read whole.
+// field-local vertex id.  A wave takes kTilesPerWave consecutive tiles and
+// walks each in rows of kWave consecutive records (one coalesced load per
+// row, the next row's load in flight while a row is written; a row's codes
+// leave as one run at the running offset).  Tiles whose scanned counts are
+// all zero are skipped unread, rows without critical cells cost no scan.
 __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
     const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
-    const uint16_t *__restrict__ cand, const uint32_t *__restrict__ ncand, const int64_t *__restrict__ foff,
-    int nfields, int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
-    int64_t cap2, int64_t cap3)
+    const int64_t *__restrict__ foff, int nfields, int64_t *crit0, int64_t *crit1, int64_t *crit2,
+    int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
 {
     __shared__ int64_t so[kMaxBatchFields + 1];
     __shared__ EdgeTris E;
-    const uint32_t n = ncand[blockIdx.x];
-    if (n == 0) return;  // uniform
     for (int i = threadIdx.x; i <= nfields; i += kThreads) so[i] = foff[i];
     load_edge_tris(E);
     __syncthreads();
-    if (n > (uint32_t)kCand) {
-        const int64_t r0 = (int64_t)blockIdx.x * kTileRecs + (int64_t)threadIdx.x * kPerThread;
-        uint64_t lo[kPerThread], hi[kPerThread], pk[kPerThread], at[kPerThread][4];
-        load_recs(rec, nbox, r0, lo, hi, pk);
-        fill_slots(pk, offs, ntiles, at);
-#pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            const int64_t r = r0 + k;
-            if (r >= nbox || pk[k] == 0) continue;
-            const int f = record_field(so, nfields, r);
-            uint32_t c[4];
-#pragma unroll
-            for (int d = 0; d < 4; ++d) c[d] = lane16(pk[k], d);
-            write_codes<true>(lo[k], hi[k], c, at[k], (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0,
-                              cap1, cap2, cap3);
-        }
-        return;
-    }
-    if (threadIdx.x >= kWave) return;
-    const int lane = threadIdx.x;
-    const bool active = (uint32_t)lane < n;
-    uint64_t lo = 0, hi = 0, pk = 0;
-    int64_t r = 0;
-    if (active) {
-        r = (int64_t)blockIdx.x * kTileRecs + cand[(int64_t)blockIdx.x * kCand + lane];
-        if (r < nbox) {
-            const uint4 w = rec[r];
-            lo = (uint64_t)w.x | ((uint64_t)w.y << 32);
-            hi = (uint64_t)w.z | ((uint64_t)w.w << 32);
-            uint32_t c[4];
-            count_critical(lo, hi, c);
-            pk = pack4(c);
-        }
-    }
-    uint64_t inc = pk;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint64_t t = __shfl_up(inc, off);
-        if (lane >= off) inc += t;
-    }
-    const uint64_t ex = inc - pk;
-    if (pk == 0) return;
+    const int lane = lane_id();
+    const int64_t tile0 =
+        (int64_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave)) *
+        kTilesPerWave;
+    if (tile0 >= ntiles) return;
     uint64_t at[4];
-    uint32_t c[4];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        at[d] = offs[(int64_t)d * ntiles + blockIdx.x] - offs[(int64_t)d * ntiles] + lane16(ex, d);
-        c[d] = lane16(pk, d);
+    for (int d = 0; d < 4; ++d) at[d] = offs[(int64_t)d * ntiles + tile0] - offs[(int64_t)d * ntiles];
+    for (int t = 0; t < kTilesPerWave; ++t) {
+        const int64_t tile = tile0 + t;
+        if (tile >= ntiles) break;
+        uint64_t any = 0;  // offs has 4 ntiles + 1 entries: tile + 1 is always in range
+#pragma unroll
+        for (int d = 0; d < 4; ++d) any |= offs[(int64_t)d * ntiles + tile + 1] - offs[(int64_t)d * ntiles + tile];
+        if (any == 0) continue;
+        const int64_t r0 = tile * kTileRecs + lane;
+        uint4 cur = make_uint4(0, 0, 0, 0), nxt = make_uint4(0, 0, 0, 0);
+        if (r0 < nbox) cur = rec[r0];
+#pragma unroll 1
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t r = r0 + (int64_t)k * kWave;
+            nxt = make_uint4(0, 0, 0, 0);
+            if (k + 1 < kRows && r + kWave < nbox) nxt = rec[r + kWave];
+            const uint64_t lo = (uint64_t)cur.x | ((uint64_t)cur.y << 32);
+            const uint64_t hi = (uint64_t)cur.z | ((uint64_t)cur.w << 32);
+            uint64_t pk = 0;
+            if (r < nbox) {
+                uint32_t c[4];
+                count_critical(lo, hi, c);
+                pk = pack4(c);
+            }
+            cur = nxt;
+            if (!__ballot(pk != 0)) continue;
+            uint64_t inc = pk;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint64_t u = __shfl_up(inc, off);
+                if (lane >= off) inc += u;
+            }
+            const uint64_t tot = __shfl(inc, kWave - 1);
+            if (pk != 0) {
+                const uint64_t ex = inc - pk;
+                uint64_t a[4];
+                uint32_t c[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    a[d] = at[d] + lane16(ex, d);
+                    c[d] = lane16(pk, d);
+                }
+                const int f = record_field(so, nfields, r);
+                write_codes(lo, hi, c, a, (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1,
+                                  cap2, cap3);
+            }
+#pragma unroll
+            for (int d = 0; d < 4; ++d) at[d] += lane16(tot, d);
+        }
     }
-    const int f = record_field(so, nfields, r);
-    write_codes<true>(lo, hi, c, at, (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 }
 
 // First slot of every field in every list: the scanned count of its first
@@ -844,14 +888,13 @@ int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, i
     const CritLayout L = crit_layout(ntiles);
     uint64_t *tc = (uint64_t *)ws;
     uint64_t *partials = (uint64_t *)(ws + L.partials);
-    uint16_t *cand = (uint16_t *)(ws + L.cand);
-    uint32_t *ncand = (uint32_t *)(ws + L.ncand);
     hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       n, tc, ntiles, cand, ncand);
+                       n, tc, ntiles, (uint16_t *)nullptr, (uint32_t *)nullptr);
     exclusive_scan<uint64_t>(tc, len, partials, s);
-    hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)ntiles), dim3(kThreads), 0, s,
-                       (const uint4 *)rec, n, tc, ntiles, cand, ncand, foff, nfields, crit[0], crit[1],
-                       crit[2], crit[3], cap[0], cap[1], cap[2], cap[3]);
+    const int64_t per_block = (int64_t)kWavesPerBlock * kTilesPerWave;
+    hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)((ntiles + per_block - 1) / per_block)),
+                       dim3(kThreads), 0, s, (const uint4 *)rec, n, tc, ntiles, foff, nfields, crit[0],
+                       crit[1], crit[2], crit[3], cap[0], cap[1], cap[2], cap[3]);
     hipLaunchKernelGGL(k_crit_fstart_batch, dim3((unsigned)nfields), dim3(kThreads), 0, s, (const uint4 *)rec,
                        tc, ntiles, foff, nfields, offsets);
     hipLaunchKernelGGL(k_crit_finish_batch, dim3(1), dim3(256), 0, s, tc, ntiles, nfields, offsets,

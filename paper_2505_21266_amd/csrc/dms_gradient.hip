@@ -189,6 +189,42 @@ __device__ __forceinline__ uint32_t low_of_ranks(uint64_t rank_of)
 
 __device__ __forceinline__ bool robins(uint64_t rank_of, int mmax, const SharedTables &T, uint4 &out);
 
+// The cell of S with the smallest key, as a one-bit set (S if S has at
+// most one cell), bit-sliced from the top rank plane down: keep the cells
+// without rank b when there are any.  mmax (uniform over the wave) bounds
+// the ranks, so the walk enters at plane mmax - 1; it stops early once no
+// lane of the wave has two candidates left (checked every second plane).
+__device__ __forceinline__ uint64_t smallest_by_key(uint64_t S, const uint64_t *nkp, int mmax)
+{
+#define DMS_PLANE(B)                                                                                     \
+    do {                                                                                                 \
+        const uint64_t z = S & nkp[B];                                                                   \
+        S = z ? z : S;                                                                                   \
+    } while (0)
+#define DMS_DONE() if (!__ballot((S & (S - 1)) != 0)) return S
+    switch (mmax) {
+    default:
+    case 14: DMS_PLANE(13); [[fallthrough]];
+    case 13: DMS_PLANE(12); DMS_DONE(); [[fallthrough]];
+    case 12: DMS_PLANE(11); [[fallthrough]];
+    case 11: DMS_PLANE(10); DMS_DONE(); [[fallthrough]];
+    case 10: DMS_PLANE(9); [[fallthrough]];
+    case 9: DMS_PLANE(8); DMS_DONE(); [[fallthrough]];
+    case 8: DMS_PLANE(7); [[fallthrough]];
+    case 7: DMS_PLANE(6); DMS_DONE(); [[fallthrough]];
+    case 6: DMS_PLANE(5); [[fallthrough]];
+    case 5: DMS_PLANE(4); DMS_DONE(); [[fallthrough]];
+    case 4: DMS_PLANE(3); [[fallthrough]];
+    case 3: DMS_PLANE(2); DMS_DONE(); [[fallthrough]];
+    case 2: DMS_PLANE(1); [[fallthrough]];
+    case 1: DMS_PLANE(0); [[fallthrough]];
+    case 0: break;
+    }
+#undef DMS_DONE
+#undef DMS_PLANE
+    return S;
+}
+
 // Robins' ProcessLowerStars for one vertex, from the orders of x and its 14
 // neighbours (kAbsent for neighbours outside the grid); mmax as in robins.
 // Returns whether L(x) holds a critical cell.
@@ -259,13 +295,7 @@ __device__ __forceinline__ bool robins(uint64_t rank_of, int mmax, const SharedT
         const uint64_t one = ftq & cnt.b0 & ~cnt.b1;
         uint64_t S = one ? one : (ftq & ~cnt.b0 & ~cnt.b1);
         if (S == 0 && fr == 0) break;
-#pragma unroll
-        for (int b = 13; b >= 0; --b) {
-            if (b < mmax) {
-                const uint64_t z = S & nkp[b];
-                S = z ? z : S;
-            }
-        }
+        S = smallest_by_key(S, nkp, mmax);
         const bool have_a = S != 0;
         const int a = have_a ? __ffsll((unsigned long long)S) - 1 : 0;
         if (one) {
