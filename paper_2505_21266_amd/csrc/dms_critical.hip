@@ -267,6 +267,90 @@ __device__ __forceinline__ void write_codes(uint64_t lo, uint64_t hi, const uint
     }
 }
 
+// Byte tables that decode a record without walking its fields:
+//   he[j][b], record byte j < 7 (edge fields 2j and 2j + 1): bits 0..35 the
+//     head triangles the two fields name, bits 36 + k the edge 2j + k is
+//     critical (field 2), bits 38 + k it is in L(x) (field non-zero);
+//   hq[j][b], record byte 7 + j (triangle fields 4j .. 4j + 3): bits 0..23
+//     the head tets they name, bits 24 + i triangle 4j + i is a tail
+//     (field non-zero).
+struct DecodeTables {
+    uint64_t he[7][256];
+    uint32_t hq[9][256];
+};
+
+constexpr DecodeTables make_decode_tables()
+{
+    DecodeTables D{};
+    const Tables &T = kTables;
+    for (int j = 0; j < 7; ++j)
+        for (uint32_t b = 0; b < 256; ++b) {
+            uint64_t v = 0;
+            for (int k = 0; k < 2; ++k) {
+                const int e = 2 * j + k;
+                const uint32_t f = (b >> (4 * k)) & 15u;
+                if (f == 2) v |= 1ull << (36 + k);
+                if (f != 0) v |= 1ull << (38 + k);
+                if (f >= 3 && (int)(f - 3) < T.edge_ntri[e]) v |= 1ull << T.edge_tris[e][f - 3];
+            }
+            D.he[j][b] = v;
+        }
+    for (int j = 0; j < 9; ++j)
+        for (uint32_t b = 0; b < 256; ++b) {
+            uint32_t v = 0;
+            for (int i = 0; i < 4; ++i) {
+                const int t = 4 * j + i;
+                const uint32_t g = (b >> (2 * i)) & 3u;
+                if (g == 0) continue;
+                v |= 1u << (24 + i);
+                if (g <= 2) v |= 1u << T.tri_tets[t][g - 1];
+            }
+            D.hq[j][b] = v;
+        }
+    return D;
+}
+
+__device__ const DecodeTables g_decode = make_decode_tables();
+
+__device__ __forceinline__ void load_decode(DecodeTables &D)
+{
+    const uint32_t *src = (const uint32_t *)&g_decode;
+    uint32_t *dst = (uint32_t *)&D;
+    for (int i = threadIdx.x; i < (int)(sizeof(DecodeTables) / 4); i += blockDim.x) dst[i] = src[i];
+}
+
+// Critical cells of one record: edges ce (by neighbour), triangles ct and
+// tets cq (by star index); returns the packed counts (pack4).
+__device__ __forceinline__ uint64_t decode_record(uint64_t lo, uint64_t hi, const DecodeTables &D, uint32_t &ce,
+                                                  uint64_t &ct, uint32_t &cq)
+{
+    uint64_t head_t = 0;
+    uint32_t low = 0;
+    ce = 0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const uint64_t v = D.he[j][(uint32_t)(lo >> (8 * j)) & 255u];
+        head_t |= v;
+        ce |= ((uint32_t)(v >> 36) & 3u) << (2 * j);
+        low |= ((uint32_t)(v >> 38) & 3u) << (2 * j);
+    }
+    uint32_t head_q = 0;
+    uint64_t tail_t = 0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const uint32_t b = j == 0 ? (uint32_t)(lo >> 56) : (uint32_t)(hi >> (8 * (j - 1))) & 255u;
+        const uint32_t v = D.hq[j][b];
+        head_q |= v;
+        tail_t |= (uint64_t)(v >> 24) << (4 * j);
+    }
+    const uint64_t cells = g_lower_cells.m[low];
+    ct = cells & ~head_t & ~tail_t & ((1ull << 36) - 1);
+    cq = (uint32_t)(cells >> 36) & ~head_q & 0xffffffu;
+    const uint64_t c0 = low == 0 ? 1u : 0u;  // L(x) = {x}: nothing else is in it
+    return c0 | ((uint64_t)__popc(ce) << 16) | ((uint64_t)__popcll((unsigned long long)ct) << 32) |
+           ((uint64_t)__popc(cq) << 48);
+}
+
 // Per-record counts packed in 16-bit lanes (dimension d in bits 16d..16d+15);
 // a block's sums fit: at most 36 x 1024 cells of one dimension.
 __device__ __forceinline__ uint64_t pack4(const uint32_t *c)
@@ -446,22 +530,6 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill(
     write_codes(lo, hi, c, at, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 }
 
-// ---------------------------------------------------------------------------
-// Masked extraction: the gradient set bit r of the mask for every record r
-// holding a critical cell, so the other records need not be read.  A wave
-// takes kTilesPerWave consecutive tiles, whose mask words it holds one per
-// lane.  When they flag at most kWave records (the usual case: most
-// vertices hold no critical cell), lane j takes the j-th flagged record and
-// one load serves the whole wave; otherwise the wave walks the tiles in rows
-// of kWave records (row k: words 2k and 2k + 1), skipping empty rows.  The
-// tiles' slots in the scanned counts are consecutive, so one running offset
-// serves both tiles.
-constexpr int kRows = kTileRecs / kWave;
-constexpr int kTileWords = kTileRecs / 32;
-constexpr int kTilesPerWave = kWave / kTileWords;
-constexpr int kWavesPerBlock = kThreads / kWave;
-static_assert(kWave == 64 && kTileWords == 2 * kRows && kTilesPerWave == 2, "one mask word per lane");
-
 // Position of the n-th set bit (n < popc(x)), by halving.
 __device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t n)
 {
@@ -477,6 +545,75 @@ __device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t n)
     }
     return pos;
 }
+
+// Writes the critical cells of a wave's records, one record per lane (ce,
+// ct, cq from decode_record; v its vertex id as the codes carry it; pk its
+// packed counts, zero for lanes without a record), in lane order: the codes
+// of list d go to slots at[d] .. at[d] + (its total) - 1, one code per lane
+// per round, so each store is contiguous.  Code j of list d belongs to the
+// first lane whose inclusive count exceeds j (a binary search over the
+// wave's scan) and names that record's (j - earlier)-th cell.  Returns the
+// wave's packed totals.  Every lane of the wave must call it.
+__device__ __forceinline__ uint64_t emit_codes(uint32_t ce, uint64_t ct, uint32_t cq, int64_t v, uint64_t pk,
+                                               const uint64_t *at, int64_t *crit0, int64_t *crit1,
+                                               int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1,
+                                               int64_t cap2, int64_t cap3)
+{
+    const int lane = lane_id();
+    uint64_t inc = pk;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t u = __shfl_up(inc, off);
+        if (lane >= off) inc += u;
+    }
+    const uint64_t tot = __shfl(inc, kWave - 1);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t total = lane16(tot, d);
+        const uint32_t incd = lane16(inc, d);
+        int64_t *const out = d == 0 ? crit0 : d == 1 ? crit1 : d == 2 ? crit2 : crit3;
+        const int64_t cap = d == 0 ? cap0 : d == 1 ? cap1 : d == 2 ? cap2 : cap3;
+        for (uint32_t j0 = 0; j0 < total; j0 += kWave) {
+            const uint32_t j = j0 + (uint32_t)lane;
+            int w = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+                if (__shfl(incd, w + step - 1) <= j) w += step;
+            const uint32_t prev = __shfl(incd, w > 0 ? w - 1 : 0);
+            const uint32_t n = j - (w > 0 ? prev : 0u);
+            const int64_t ov = __shfl(v, w);
+            uint32_t local = 0;
+            if (d == 1) {
+                local = select_bit(__shfl(ce, w), n);
+            } else if (d == 2) {
+                const uint64_t m = __shfl(ct, w);
+                const uint32_t m0 = (uint32_t)m, c = (uint32_t)__popc(m0);
+                local = n < c ? select_bit(m0, n) : 32u + select_bit((uint32_t)(m >> 32), n - c);
+            } else if (d == 3) {
+                local = select_bit(__shfl(cq, w), n);
+            }
+            const int64_t a = (int64_t)at[d] + (int64_t)j;
+            if (j < total && a < cap) out[a] = (ov << 8) | (int64_t)local;
+        }
+    }
+    return tot;
+}
+
+// ---------------------------------------------------------------------------
+// Masked extraction: the gradient set bit r of the mask for every record r
+// holding a critical cell, so the other records need not be read.  A wave
+// takes kTilesPerWave consecutive tiles, whose mask words it holds one per
+// lane.  When they flag at most kWave records (the usual case: most
+// vertices hold no critical cell), lane j takes the j-th flagged record and
+// one load serves the whole wave; otherwise the wave walks the tiles in rows
+// of kWave records (row k: words 2k and 2k + 1), skipping empty rows.  The
+// tiles' slots in the scanned counts are consecutive, so one running offset
+// serves both tiles.
+constexpr int kRows = kTileRecs / kWave;
+constexpr int kTileWords = kTileRecs / 32;
+constexpr int kTilesPerWave = kWave / kTileWords;
+constexpr int kWavesPerBlock = kThreads / kWave;
+static_assert(kWave == 64 && kTileWords == 2 * kRows && kTilesPerWave == 2, "one mask word per lane");
 
 // The wave's flagged records: word = mask word `lane` of the wave's tiles.
 // Returns their number; when it is at most kWave, rel (of lane j < number)
@@ -571,9 +708,9 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_masked(
     int64_t lo2, int64_t nx, int64_t ny, int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3,
     int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
 {
-    __shared__ EdgeTris E;
-    load_edge_tris(E);
-    __syncthreads();
+    // few records per block: the decode tables are read where they are
+    // (cached) rather than staged in LDS
+    const DecodeTables &D = g_decode;
     const int lane = lane_id();
     const int64_t tile0 =
         (int64_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave)) *
@@ -602,27 +739,19 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_masked(
             if (empty) continue;
             r = r0 + k * kWave + lane;
         }
-        uint64_t lo = 0, hi = 0, pk = 0;
-        if (take && r < nbox) pk = count_record(rec, r, lo, hi);
-        uint64_t inc = pk;  // inclusive scan of the packed counts over the wave
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint64_t t = __shfl_up(inc, off);
-            if (lane >= off) inc += t;
+        uint64_t pk = 0;
+        uint32_t ce = 0, cq = 0;
+        uint64_t ct = 0;
+        int64_t v = 0;
+        if (take && r < nbox) {
+            const uint4 w = rec[r];
+            pk = decode_record((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), D,
+                               ce, ct, cq);
+            v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
         }
-        const uint64_t tot = __shfl(inc, kWave - 1);
-        if (pk != 0) {
-            const uint64_t ex = inc - pk;
-            uint64_t a[4];
-            uint32_t c[4];
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                a[d] = at[d] + lane16(ex, d);
-                c[d] = lane16(pk, d);
-            }
-            const int64_t v = box_vertex(r, w0, w1, lo0, lo1, lo2, nx, ny);
-            write_codes(lo, hi, c, a, v << 8, E, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
-        }
+        if (!__ballot(pk != 0)) continue;
+        const uint64_t tot =
+            emit_codes(ce, ct, cq, v, pk, at, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
 #pragma unroll
         for (int d = 0; d < 4; ++d) at[d] += lane16(tot, d);
     }
@@ -660,69 +789,56 @@ __device__ __forceinline__ int record_field(const int64_t *so, int nfields, int6
 // row, the next row's load in flight while a row is written; a row's codes
 // leave as one run at the running offset).  Tiles whose scanned counts are
 // all zero are skipped unread, rows without critical cells cost no scan.
+constexpr int kBatchTilesPerWave = 8;
+
 __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
     const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
     const int64_t *__restrict__ foff, int nfields, int64_t *crit0, int64_t *crit1, int64_t *crit2,
     int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
 {
     __shared__ int64_t so[kMaxBatchFields + 1];
-    __shared__ EdgeTris E;
+    __shared__ DecodeTables D;
     for (int i = threadIdx.x; i <= nfields; i += kThreads) so[i] = foff[i];
-    load_edge_tris(E);
+    load_decode(D);
     __syncthreads();
     const int lane = lane_id();
     const int64_t tile0 =
         (int64_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave)) *
-        kTilesPerWave;
+        kBatchTilesPerWave;
     if (tile0 >= ntiles) return;
     uint64_t at[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) at[d] = offs[(int64_t)d * ntiles + tile0] - offs[(int64_t)d * ntiles];
-    for (int t = 0; t < kTilesPerWave; ++t) {
+    // field of the wave's first record (uniform); later rows move it forward
+    int f0 = 0;
+    for (int step = 1 << 10; step > 0; step >>= 1)
+        if (f0 + step < nfields && so[f0 + step] <= tile0 * kTileRecs) f0 += step;
+    for (int t = 0; t < kBatchTilesPerWave; ++t) {
         const int64_t tile = tile0 + t;
         if (tile >= ntiles) break;
         uint64_t any = 0;  // offs has 4 ntiles + 1 entries: tile + 1 is always in range
 #pragma unroll
         for (int d = 0; d < 4; ++d) any |= offs[(int64_t)d * ntiles + tile + 1] - offs[(int64_t)d * ntiles + tile];
         if (any == 0) continue;
-        const int64_t r0 = tile * kTileRecs + lane;
-        uint4 cur = make_uint4(0, 0, 0, 0), nxt = make_uint4(0, 0, 0, 0);
-        if (r0 < nbox) cur = rec[r0];
 #pragma unroll 1
         for (int k = 0; k < kRows; ++k) {
-            const int64_t r = r0 + (int64_t)k * kWave;
-            nxt = make_uint4(0, 0, 0, 0);
-            if (k + 1 < kRows && r + kWave < nbox) nxt = rec[r + kWave];
-            const uint64_t lo = (uint64_t)cur.x | ((uint64_t)cur.y << 32);
-            const uint64_t hi = (uint64_t)cur.z | ((uint64_t)cur.w << 32);
+            const int64_t row = tile * kTileRecs + (int64_t)k * kWave;
+            if (row >= nbox) break;
+            const int64_t r = row + lane;
             uint64_t pk = 0;
+            uint32_t ce = 0, cq = 0;
+            uint64_t ct = 0;
             if (r < nbox) {
-                uint32_t c[4];
-                count_critical(lo, hi, c);
-                pk = pack4(c);
+                const uint4 w = rec[r];
+                pk = decode_record((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32),
+                                   D, ce, ct, cq);
             }
-            cur = nxt;
             if (!__ballot(pk != 0)) continue;
-            uint64_t inc = pk;
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const uint64_t u = __shfl_up(inc, off);
-                if (lane >= off) inc += u;
-            }
-            const uint64_t tot = __shfl(inc, kWave - 1);
-            if (pk != 0) {
-                const uint64_t ex = inc - pk;
-                uint64_t a[4];
-                uint32_t c[4];
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    a[d] = at[d] + lane16(ex, d);
-                    c[d] = lane16(pk, d);
-                }
-                const int f = record_field(so, nfields, r);
-                write_codes(lo, hi, c, a, (r - so[f]) << 8, E, crit0, crit1, crit2, crit3, cap0, cap1,
-                                  cap2, cap3);
-            }
+            while (f0 + 1 < nfields && so[f0 + 1] <= row) ++f0;  // uniform
+            int f = f0;
+            while (f + 1 < nfields && so[f + 1] <= r) ++f;  // fields shorter than a row
+            const uint64_t tot = emit_codes(ce, ct, cq, r - so[f], pk, at, crit0, crit1, crit2, crit3, cap0, cap1,
+                                            cap2, cap3);
 #pragma unroll
             for (int d = 0; d < 4; ++d) at[d] += lane16(tot, d);
         }
@@ -891,7 +1007,7 @@ int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, i
     hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
                        n, tc, ntiles, (uint16_t *)nullptr, (uint32_t *)nullptr);
     exclusive_scan<uint64_t>(tc, len, partials, s);
-    const int64_t per_block = (int64_t)kWavesPerBlock * kTilesPerWave;
+    const int64_t per_block = (int64_t)kWavesPerBlock * kBatchTilesPerWave;
     hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)((ntiles + per_block - 1) / per_block)),
                        dim3(kThreads), 0, s, (const uint4 *)rec, n, tc, ntiles, foff, nfields, crit[0],
                        crit[1], crit[2], crit[3], cap[0], cap[1], cap[2], cap[3]);
