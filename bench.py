@@ -44,9 +44,9 @@ def parse():
     ap.add_argument("--large", action="store_true",
                     help="time the order-free path (gradient from the values + extraction) on the "
                          "2048x1920x1536 float32 field instead (one JSON line of its own)")
-    ap.add_argument("--only", choices=["batched", "differentiable"], default=None,
-                    help="run only the batched (96-field) or the differentiable (128^3 f64) part and "
-                         "print its object as the JSON line (for profiling)")
+    ap.add_argument("--only", choices=["batched", "differentiable", "small"], default=None,
+                    help="run only the batched (96-field), the differentiable (128^3 f64) or the "
+                         "64^3 and 512^3 part and print its object as the JSON line")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -243,6 +243,62 @@ def bench_differentiable(dev, reps):
             "backward_gpu_ms": round(float(np.median(bwd)), 4), "reps": reps}
 
 
+def bench_small_configs(dev, reps):
+    """The 64^3 noise and 512^3 Gaussian fields: the step (order, gradient
+    with the critical mask, masked extraction) timed per stage with HIP
+    events on the stream (median of `reps`), and the CPU oracle on the same
+    whole field on every host core."""
+    import torch
+
+    import paper_2505_21266_amd as dms
+    from paper_2505_21266_amd import inputs
+    out = {}
+    threads = len(os.sched_getaffinity(0))
+    for name, field in (("noise64", inputs.config1()), ("gauss512", inputs.config2())):
+        nz, ny, nx = field.shape
+        dims = (nx, ny, nz)
+        n = nx * ny * nz
+        values = torch.from_numpy(field).to(dev)
+        order_t = torch.empty(values.shape, dtype=torch.int32, device=dev)
+        rec = torch.empty((n, 4), dtype=torch.int32, device=dev)
+        mask = dms.critical_mask(n, dev)
+        gws = dms.gradient_workspace(order_t)
+        flags = dms.new_flags(dev)
+        dms.order(values, out=order_t)
+        dms.discrete_gradient(order_t, out=rec, workspace=gws, mask=mask)
+        lists, counts = dms.critical_simplices(rec, dims, mask=mask)
+        cap = counts.cpu().numpy().copy()
+        counts_t = torch.zeros(4, dtype=torch.int64, device=dev)
+        stream = torch.cuda.current_stream(dev)
+        stages = []
+        for _ in range(reps + 1):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record(stream)
+            dms.order(values, out=order_t, flags=flags, check=False)
+            e[1].record(stream)
+            dms.discrete_gradient(order_t, out=rec, workspace=gws, mask=mask)
+            e[2].record(stream)
+            dms.critical_simplices(rec, dims, cap=cap, flags=flags, counts=counts_t, mask=mask)
+            e[3].record(stream)
+            torch.cuda.synchronize()
+            stages.append([e[i].elapsed_time(e[i + 1]) for i in range(3)])
+        if int(flags.item()) != 0:
+            raise RuntimeError("device flags set: %d" % int(flags.item()))
+        med = np.median(np.asarray(stages[1:]), axis=0)
+        del values, order_t, rec, mask, gws, lists
+        torch.cuda.empty_cache()
+        owned, st = _oracle_stages(field, (0, 0, 0), dims, threads)
+        out[name] = {"vertices": n, "gpu_ms": {"order": round(float(med[0]), 3),
+                                               "gradient": round(float(med[1]), 3),
+                                               "critical": round(float(med[2]), 3)},
+                     "gvertices_per_s": round(n / (float(med.sum()) / 1e3) / 1e9, 3),
+                     "critical_counts": [int(c) for c in cap],
+                     "oracle_s": {"order": round(st[0], 3), "lower_stars": round(st[1], 3),
+                                  "extraction": round(st[2], 3)},
+                     "oracle_threads": threads}
+    return out
+
+
 def bench_large(args, dev):
     """The paper's largest shape, 2048 x 1920 x 1536 float32 (6.04e9
     vertices): beyond int32 orders, so the step is the gradient straight
@@ -328,6 +384,9 @@ def main():
         return
     if args.only == "batched":
         print(json.dumps(bench_batched(dev, max(args.steps, 3))), flush=True)
+        return
+    if args.only == "small":
+        print(json.dumps(bench_small_configs(dev, max(args.steps, 3))), flush=True)
         return
     if args.only == "differentiable":
         print(json.dumps(bench_differentiable(dev, max(args.steps, 3))), flush=True)
@@ -424,8 +483,8 @@ def main():
     ms_step = wall / args.steps * 1e3
     value = owned / (ms_step / 1e3) / 1e9
 
-    # dominant call: dms_discrete_gradient (k_queue_reset + k_gradient + k_gradient_queue on the
-    # same stream; the events bracket exactly these launches)
+    # dominant call: dms_discrete_gradient (k_mark_zero + k_queue_reset + k_gradient +
+    # k_gradient_queue on the same stream; the events bracket exactly these launches)
     stage_bytes = {k: ALG_BYTES[k] * owned for k in ALG_BYTES}
     # the masked extraction reads the mask and the flagged records only
     stage_bytes["critical"] = MASK_BYTES * owned + 16.0 * flagged
@@ -434,7 +493,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic_gb(),
-                "kernel": "dms_discrete_gradient: k_queue_reset + k_gradient<64,16> + k_gradient_queue",
+                "kernel": "dms_discrete_gradient: k_mark_zero + k_queue_reset + k_gradient<64,16> + k_gradient_queue",
                 "kernel_ms": round(ms[dom], 3)}
     out = {
         "metric": "discrete-gradient Gvertices/s (order + gradient + critical) at 1024^3 owned f32",
