@@ -1,8 +1,10 @@
 """The paper's largest shape, 2048 x 1920 x 1536 (6.04e9 vertices, beyond
 int32 orders), on one GPU through the path that needs no order: the gradient
 from the float32 values and the extraction.  60000 sampled vertices have the
-oracle's records (computed from the values), and the critical lists
-restricted to them are exactly the critical cells of those records."""
+oracle's records (computed from the values), the critical lists
+restricted to them are exactly the critical cells of those records, and the
+critical mask flags exactly those of them that hold one (the launch
+configuration of the benchmark's --large line)."""
 import os
 import sys
 
@@ -34,8 +36,9 @@ def test_values_path_at_the_paper_largest_shape():
     print("oracle sampled done", flush=True)
     vt = torch.from_numpy(v).cuda()
     del v
-    rec = dms.discrete_gradient_values(vt, check=True)
-    lists, counts = dms.critical_simplices(rec, dims)
+    mask = dms.critical_mask(n, vt.device)
+    rec = dms.discrete_gradient_values(vt, check=True, mask=mask)
+    lists, counts = dms.critical_simplices(rec, dims, mask=mask)
     c = counts.cpu().numpy()
     print("critical counts", c.tolist(), flush=True)
     assert c[0] - c[1] + c[2] - c[3] == 1  # Euler characteristic of the ball
@@ -60,3 +63,11 @@ def test_values_path_at_the_paper_largest_shape():
         mine = set(int(x) for x in codes[np.isin(codes >> 8, vids)])
         assert mine == expect[d], d
     assert sum(len(e) for e in expect) > 20
+    # the critical mask flags exactly the sampled records that hold a critical cell
+    vt_ids = torch.from_numpy(vids).cuda()
+    words = mask[vt_ids >> 5].cpu().numpy().view(np.uint32)
+    bits = (words >> (vids & 31).astype(np.uint32)) & 1
+    has = set()
+    for d in range(4):
+        has |= set(c >> 8 for c in expect[d])
+    assert [bool(b) for b in bits] == [int(x) in has for x in vids]
