@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 import paper_2505_21266_amd as dms
+from batch_cache import pin_variant
 from paper_2505_21266_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -61,6 +62,25 @@ def test_batch_exact_per_field():
     b = dms.Batch(SIDES)
     out = b.run(vals)
     _check_fields(SIDES, fields, *out)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_batch_exact_each_tile_shape(variant, tmp_path):
+    """Each of the three tile shapes, pinned through the tuning cache, on the
+    ragged fields (noise tiles pair their general vertices in place, tiles
+    of the smooth and tied fields queue them) and on 300 tiny fields."""
+    fields = [_field(s, i % 3, 300 + i) for i, s in enumerate(SIDES)]
+    vals = torch.from_numpy(np.concatenate([f.reshape(-1) for f in fields])).cuda()
+    b = dms.Batch(SIDES, cache=pin_variant(tmp_path / "tune.txt", SIDES, variant))
+    assert b.variant == variant
+    _check_fields(SIDES, fields, *b.run(vals))
+    rng = np.random.default_rng(78)
+    sides = [tuple(int(x) for x in rng.integers(1, 7, 3)) for _ in range(300)]
+    fields = [_field(s, i % 3, 1900 + i) for i, s in enumerate(sides)]
+    vals = torch.from_numpy(np.concatenate([f.reshape(-1) for f in fields])).cuda()
+    b = dms.Batch(sides, cache=pin_variant(tmp_path / "tune300.txt", sides, variant))
+    assert b.variant == variant
+    _check_fields(sides, fields, *b.run(vals))
 
 
 def test_batch_many_fields():

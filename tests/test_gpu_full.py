@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 import paper_2505_21266_amd as dms
+from batch_cache import pin_variant
 from paper_2505_21266_amd import inputs
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -223,9 +224,7 @@ def test_config4_exact(config4_oracle, variant, tmp_path):
     vals = _dev(np.concatenate([f.reshape(-1) for f in fields]))
     cache = None
     if variant is not None:
-        cache = str(tmp_path / "tune.txt")
-        with open(cache, "w") as fh:
-            fh.write("gfx950 %x %d\n" % (batch_signature(sides), variant))
+        cache = pin_variant(tmp_path / "tune.txt", sides, variant)
     b = dms.Batch(sides, tune=variant is None, cache=cache)
     if variant is not None:
         assert b.variant == variant
@@ -246,13 +245,3 @@ def test_config4_exact(config4_oracle, variant, tmp_path):
             assert np.array_equal(L[d][offsets[d, f]:offsets[d, f + 1]], crit[d]), (f, d)
     for d in range(4):
         assert offsets[d, -1] == counts[:, d].sum() == L[d].size
-
-
-def batch_signature(sides):
-    """The batch plan's key for its tuning cache: FNV-1a over the fields'
-    sides as little-endian int64 (x, y, z per field)."""
-    h = 1469598103934665603
-    for b in np.asarray(sides, dtype="<i8").tobytes():
-        h ^= b
-        h = (h * 1099511628211) & 0xFFFFFFFFFFFFFFFF
-    return h
