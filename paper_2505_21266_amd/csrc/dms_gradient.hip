@@ -192,8 +192,9 @@ __device__ __forceinline__ bool robins(uint64_t rank_of, int mmax, const SharedT
 // The cell of S with the smallest key, as a one-bit set (S if S has at
 // most one cell), bit-sliced from the top rank plane down: keep the cells
 // without rank b when there are any.  mmax (uniform over the wave) bounds
-// the ranks, so the walk enters at plane mmax - 1; it stops early once no
-// lane of the wave has two candidates left (checked every second plane).
+// the ranks, so the walk enters at plane mmax - 1 through a uniform switch.
+// (Stopping early once no lane of the wave has two candidates left cost
+// more in checks than it saved in planes.)
 __device__ __forceinline__ uint64_t smallest_by_key(uint64_t S, const uint64_t *nkp, int mmax)
 {
 #define DMS_PLANE(B)                                                                                     \
@@ -201,26 +202,24 @@ __device__ __forceinline__ uint64_t smallest_by_key(uint64_t S, const uint64_t *
         const uint64_t z = S & nkp[B];                                                                   \
         S = z ? z : S;                                                                                   \
     } while (0)
-#define DMS_DONE() if (!__ballot((S & (S - 1)) != 0)) return S
     switch (mmax) {
     default:
     case 14: DMS_PLANE(13); [[fallthrough]];
-    case 13: DMS_PLANE(12); DMS_DONE(); [[fallthrough]];
+    case 13: DMS_PLANE(12); [[fallthrough]];
     case 12: DMS_PLANE(11); [[fallthrough]];
-    case 11: DMS_PLANE(10); DMS_DONE(); [[fallthrough]];
+    case 11: DMS_PLANE(10); [[fallthrough]];
     case 10: DMS_PLANE(9); [[fallthrough]];
-    case 9: DMS_PLANE(8); DMS_DONE(); [[fallthrough]];
+    case 9: DMS_PLANE(8); [[fallthrough]];
     case 8: DMS_PLANE(7); [[fallthrough]];
-    case 7: DMS_PLANE(6); DMS_DONE(); [[fallthrough]];
+    case 7: DMS_PLANE(6); [[fallthrough]];
     case 6: DMS_PLANE(5); [[fallthrough]];
-    case 5: DMS_PLANE(4); DMS_DONE(); [[fallthrough]];
+    case 5: DMS_PLANE(4); [[fallthrough]];
     case 4: DMS_PLANE(3); [[fallthrough]];
-    case 3: DMS_PLANE(2); DMS_DONE(); [[fallthrough]];
+    case 3: DMS_PLANE(2); [[fallthrough]];
     case 2: DMS_PLANE(1); [[fallthrough]];
     case 1: DMS_PLANE(0); [[fallthrough]];
     case 0: break;
     }
-#undef DMS_DONE
 #undef DMS_PLANE
     return S;
 }
