@@ -160,21 +160,19 @@ __device__ __forceinline__ int64_t item_at(int64_t t0, int li, int last)
 
 // (1) per-tile histogram of the digit at `shift`; counts is digit-major:
 // counts[d * ntiles + tile].
-// With ids != null (the last pass) it also histograms the vertex ids by
-// bucket (id >> bshift) into bcounts, for the grouped inversion.
+// ids: the vertex ids, read by the field pass of a batch, whose digit is
+// each id's field.
 // kField (the last pass of a batch with 4-byte keys): the digit is the field
 // of the vertex id instead of a byte of the key.
 template <typename V, typename K, bool kFirst, int kThr, bool kField = false>
 __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, int shift,
                                                         uint32_t *counts, int64_t ntiles,
                                                         uint32_t *flags, const uint32_t *ids,
-                                                        int bshift, uint32_t *bcounts,
                                                         const int64_t *foff, int nfields)
 {
     __shared__ int64_t fo[kField ? kFieldPassFields + 1 : 1];
     constexpr int kW = kThr / kWave;
     __shared__ uint32_t hist[kW][kRadix];
-    __shared__ uint32_t bhist[kW][kRadix];
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int64_t tile = tile_of_block(ntiles);
     const int64_t t0 = tile * (kThr * kItems);
@@ -191,18 +189,10 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
 #pragma unroll
         for (int k = 0; k < kItems; ++k) bid[k] = ids[item_at(t0, local_index(wave, k, lane), last)];
     }
-    for (int i = tid; i < kW * kRadix; i += kThr) {
-        (&hist[0][0])[i] = 0;
-        (&bhist[0][0])[i] = 0;
-    }
+    for (int i = tid; i < kW * kRadix; i += kThr) (&hist[0][0])[i] = 0;
     if constexpr (kField) load_field_offsets(fo, foff, nfields);
     __syncthreads();
     bool nan_any = false;
-    if (ids) {
-#pragma unroll
-        for (int k = 0; k < kItems; ++k)
-            hist_add(bhist[wave], (bid[k] >> bshift) & (kRadix - 1), local_index(wave, k, lane) < count);
-    }
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const bool valid = local_index(wave, k, lane) < count;
@@ -224,12 +214,6 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
 #pragma unroll
     for (int w = 0; w < kW; ++w) tot += hist[w][tid];
     counts[(int64_t)tid * ntiles + tile] = tot;  // digit-major, tiles in tile order
-    if (ids) {
-        uint32_t bt = 0;
-#pragma unroll
-        for (int w = 0; w < kW; ++w) bt += bhist[w][tid];
-        bcounts[(int64_t)tid * ntiles + tile] = bt;
-    }
 }
 
 // Key storage between passes.  Every pass sorts by one byte of the stored
@@ -462,7 +446,11 @@ InvertPlan invert_plan(int64_t n)
 // Level 0: the last radix pass.  Each item's final position g comes from the
 // digit ranks as in k_scatter; the tile is then re-ranked by coarse bucket
 // and staged in LDS in bucket order, so that a bucket's pairs from this tile
-// leave as one contiguous run at the bucket's scanned offset (boffsets).
+// leave as one contiguous run.  The run's place inside its bucket is taken
+// from the bucket's fill counter (bfill, zeroed beforehand) by one atomic
+// add per bucket and tile: the order of the pairs inside a bucket does not
+// matter to the inversion, which places them by id, and bucket b starts at
+// position b << bshift because the ids are a permutation.
 // For batches the position is taken relative to the field's first vertex.
 // Per-wave counts are 16-bit (at most a tile), so that the block's LDS stays
 // just under 40 KiB at 256 threads (four blocks per CU) and 75 KiB at 512
@@ -471,7 +459,7 @@ template <typename K, int kThr, bool kField = false>
 __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint32_t *src_ids,
                                                            int64_t n, int shift,
                                                            const uint32_t *offsets,
-                                                           const uint32_t *boffsets, int64_t ntiles,
+                                                           uint32_t *bfill, int64_t ntiles,
                                                            const int64_t *foff, int nfields, int bshift,
                                                            uint32_t *pair_id, int32_t *pair_pos)
 {
@@ -534,11 +522,12 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
     {
         wave_prefix<kThr>(dwh);
         uint32_t total;
-        const uint32_t start = block_exclusive_scan<uint32_t, kThr>(wave_prefix<kThr>(bwh), &total);
+        const uint32_t nb = wave_prefix<kThr>(bwh);  // the tile's pairs of bucket tid
+        const uint32_t start = block_exclusive_scan<uint32_t, kThr>(nb, &total);
         if (tid < kRadix) {
             bstart[tid] = start;
             gbase[tid] = offsets[(int64_t)tid * ntiles + tile];
-            bbase[tid] = boffsets[(int64_t)tid * ntiles + tile] - start;
+            bbase[tid] = nb ? ((uint32_t)tid << bshift) + atomicAdd(&bfill[tid], nb) - start : 0u;
         }
     }
     __syncthreads();
@@ -576,49 +565,13 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
     }
 }
 
-// Level 1 counts: chunk c (kTile positions) lies in coarse bucket c >> qlog;
-// counts are coarse-bucket major, then fine digit, then chunk, so that one
-// exclusive scan gives every chunk its output offset for every fine digit.
-__device__ __forceinline__ int64_t fine_count_index(int64_t c, int f, int flog, int qlog)
-{
-    const int64_t cb = c >> qlog, q = c & ((1ll << qlog) - 1);
-    return (((cb << flog) | f) << qlog) | q;
-}
-
-__global__ __launch_bounds__(kThreads) void k_fine_hist(const uint32_t *pair_id, int64_t n,
-                                                        int fshift, int flog, int qlog,
-                                                        int64_t nchunks, uint32_t *counts)
-{
-    __shared__ uint32_t hist[kWaves][kRadix];
-    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const int64_t c = tile_of_block(nchunks);
-    const int64_t t0 = c * kTile;
-    const int count = tile_count(n, c);
-    const uint32_t fmask = (1u << flog) - 1u;
-    uint32_t raw[kItems];
-    if (count > 0) {
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) raw[k] = pair_id[item_at(t0, local_index(wave, k, lane), count - 1)];
-    }
-    for (int i = tid; i < kWaves * kRadix; i += kThreads) (&hist[0][0])[i] = 0;
-    __syncthreads();
-    if (count > 0) {
-#pragma unroll
-        for (int k = 0; k < kItems; ++k)
-            hist_add(hist[wave], (raw[k] >> fshift) & fmask, local_index(wave, k, lane) < count);
-    }
-    __syncthreads();
-    if (tid <= (int)fmask) {
-        uint32_t tot = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) tot += hist[w][tid];
-        counts[fine_count_index(c, tid, flog, qlog)] = tot;
-    }
-}
-
+// Level 1: a partition of each chunk of a coarse bucket by the fine digit
+// into the windows of ids.  As in level 0, a chunk's run for window w is
+// placed by one atomic add on the window's fill counter (wfill, zeroed
+// beforehand; window w starts at position w << fshift).
 __global__ __launch_bounds__(kThreads) void k_fine_scatter(const uint32_t *in_id, const int32_t *in_pos,
                                                            int64_t n, int fshift, int flog, int qlog,
-                                                           int64_t nchunks, const uint32_t *offsets,
+                                                           int64_t nchunks, uint32_t *wfill,
                                                            uint32_t *out_id, int32_t *out_pos)
 {
     __shared__ uint32_t wh[kWaves][kRadix];
@@ -636,12 +589,12 @@ __global__ __launch_bounds__(kThreads) void k_fine_scatter(const uint32_t *in_id
     const uint32_t fmask = (1u << flog) - 1u;
     uint32_t id[kItems], r[kItems];
     int32_t pos[kItems];
+    if (count == 0) return;  // block-uniform
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int li = local_index(wave, k, lane);
-        const bool valid = li < count;
-        id[k] = valid ? in_id[t0 + li] : 0u;
-        pos[k] = valid ? in_pos[t0 + li] : 0;
+    for (int k = 0; k < kItems; ++k) {  // unconditional loads (count >= 1)
+        const int64_t at = item_at(t0, local_index(wave, k, lane), count - 1);
+        id[k] = in_id[at];
+        pos[k] = in_pos[at];
     }
 #pragma unroll
     for (int k = 0; k < kItems; ++k)
@@ -650,9 +603,11 @@ __global__ __launch_bounds__(kThreads) void k_fine_scatter(const uint32_t *in_id
     __syncthreads();
     {
         uint32_t total;
-        const uint32_t start = block_exclusive_scan<uint32_t>(wave_prefix(wh), &total);
+        const uint32_t nw = wave_prefix(wh);  // the chunk's pairs of window digit tid
+        const uint32_t start = block_exclusive_scan<uint32_t>(nw, &total);
         dstart[tid] = start;
-        gbase[tid] = (tid <= (int)fmask ? offsets[fine_count_index(c, tid, flog, qlog)] : 0u) - start;
+        const int64_t w = ((c >> qlog) << flog) | tid;
+        gbase[tid] = (tid <= (int)fmask && nw) ? (uint32_t)(w << fshift) + atomicAdd(&wfill[w], nw) - start : 0u;
     }
     __syncthreads();
 #pragma unroll
@@ -719,8 +674,11 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_window(const uint32_t *_
 }
 
 struct OrderLayout {
-    size_t keys0, keys1, ids0, ids1, counts, partials, bcounts, bpartials, total;
+    size_t keys0, keys1, ids0, ids1, counts, partials, fill, total;
 };
+
+// Fill counters of the inversion: the kRadix coarse buckets, then the windows.
+inline int64_t fill_words(int64_t n, const InvertPlan &P) { return kRadix + ((n + (1ll << P.wshift) - 1) >> P.wshift); }
 
 template <typename K>
 OrderLayout order_layout(int64_t n)
@@ -729,7 +687,6 @@ OrderLayout order_layout(int64_t n)
     const InvertPlan P = invert_plan(n);
     const int64_t chunks = P.fine && P.nchunks > ntiles ? P.nchunks : ntiles;
     const int64_t clen = chunks * kRadix;
-    const int64_t blen = ntiles * kRadix;
     OrderLayout L{};
     size_t off = 0;
     L.keys0 = off; off += align_up((size_t)n * sizeof(K), 256);
@@ -738,8 +695,7 @@ OrderLayout order_layout(int64_t n)
     L.ids1 = off; off += align_up((size_t)n * 4, 256);
     L.counts = off; off += align_up((size_t)clen * 4, 256);
     L.partials = off; off += scan_partials_bytes(clen, 4);
-    L.bcounts = off; off += align_up((size_t)blen * 4, 256);
-    L.bpartials = off; off += scan_partials_bytes(blen, 4);
+    L.fill = off; off += align_up((size_t)fill_words(n, P) * 4, 256);
     L.total = off;
     return L;
 }
@@ -772,7 +728,7 @@ void radix_pass(const PassArgs &A)
     constexpr int kW = pass_threads<K>();
     const int64_t nt = (A.n + kW * kItems - 1) / (kW * kItems);
     hipLaunchKernelGGL((k_tile_hist<V, K, kFirst, kW>), dim3((unsigned)nt), dim3(kW), 0, A.s, A.src, A.n,
-                       A.shift, A.counts, nt, A.flags, nullptr, 0, nullptr, nullptr, 0);
+                       A.shift, A.counts, nt, A.flags, (const uint32_t *)nullptr, (const int64_t *)nullptr, 0);
     exclusive_scan<uint32_t>(A.counts, nt * kRadix, A.partials, A.s);
     hipLaunchKernelGGL((k_scatter<V, K, KD, kFirst, kW>), dim3((unsigned)nt), dim3(kW), 0, A.s, A.src, A.sids,
                        A.n, A.shift, A.strip, A.counts, nt, A.dkeys, A.dids, A.foff, A.nfields);
@@ -792,21 +748,27 @@ int radix_mid_pass(int ks, int kd, const PassArgs &A)
     }
 }
 
-// The last pass (histograms of the digit and of the id buckets, scans,
-// level-0 scatter of the (id, position) pairs) on stored keys KS.
+// The last pass (histogram of the digit, its scan, level-0 scatter of the
+// (id, position) pairs into the coarse buckets, placed through bfill) on
+// stored keys KS.
 template <typename KS, bool kField>
 void last_pass(const void *src, const uint32_t *sids, int64_t n, int shift, const InvertPlan &P,
-               uint32_t *counts, uint32_t *partials, uint32_t *bcounts, uint32_t *bpartials, uint32_t *flags,
-               const int64_t *foff, int nfields, uint32_t *aid, int32_t *apos, hipStream_t s)
+               uint32_t *counts, uint32_t *partials, uint32_t *bfill, uint32_t *flags, const int64_t *foff,
+               int nfields, uint32_t *aid, int32_t *apos, hipStream_t s)
 {
     constexpr int kW = pass_threads<KS>();
     const int64_t nt = (n + kW * kItems - 1) / (kW * kItems);
     hipLaunchKernelGGL((k_tile_hist<KS, KS, false, kW, kField>), dim3((unsigned)nt), dim3(kW), 0, s, src, n,
-                       shift, counts, nt, flags, sids, P.bshift, bcounts, foff, nfields);
+                       shift, counts, nt, flags, kField ? sids : nullptr, foff, nfields);
     exclusive_scan<uint32_t>(counts, nt * kRadix, partials, s);
-    exclusive_scan<uint32_t>(bcounts, nt * kRadix, bpartials, s);
     hipLaunchKernelGGL((k_scatter_last<KS, kW, kField>), dim3((unsigned)nt), dim3(kW), 0, s, (const KS *)src,
-                       sids, n, shift, counts, bcounts, nt, foff, nfields, P.bshift, aid, apos);
+                       sids, n, shift, counts, bfill, nt, foff, nfields, P.bshift, aid, apos);
+}
+
+__global__ void k_zero_words(uint32_t *__restrict__ w, int64_t nw)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) w[i] = 0u;
 }
 
 // field_last: a batch of at most kFieldPassFields fields with 4-byte keys;
@@ -827,8 +789,7 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
     uint32_t *ids[2] = {(uint32_t *)(ws + L.ids0), (uint32_t *)(ws + L.ids1)};
     uint32_t *counts = (uint32_t *)(ws + L.counts);
     uint32_t *partials = (uint32_t *)(ws + L.partials);
-    uint32_t *bcounts = (uint32_t *)(ws + L.bcounts);
-    uint32_t *bpartials = (uint32_t *)(ws + L.bpartials);
+    uint32_t *bfill = (uint32_t *)(ws + L.fill), *wfill = bfill + kRadix;
     for (int p = 0; p < passes; ++p) {
         // digits: the stored key's low byte, or byte p of the whole key
         const int shift = strip ? 0 : 8 * p;
@@ -853,24 +814,23 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
         // source buffers once they are read
         uint32_t *aid = (uint32_t *)keys[p & 1];
         int32_t *apos = (int32_t *)ids[p & 1];
+        const int64_t nfill = fill_words(n, P);
+        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((nfill + 255) / 256)), dim3(256), 0, s, bfill, nfill);
         if (field_last)
-            last_pass<uint32_t, true>(src, sids, n, 0, P, counts, partials, bcounts, bpartials, flags, foff,
-                                      nfields, aid, apos, s);
+            last_pass<uint32_t, true>(src, sids, n, 0, P, counts, partials, bfill, flags, foff, nfields, aid,
+                                      apos, s);
         else if (strip)
-            last_pass<uint8_t, false>(src, sids, n, 0, P, counts, partials, bcounts, bpartials, flags, foff,
-                                      nfields, aid, apos, s);
+            last_pass<uint8_t, false>(src, sids, n, 0, P, counts, partials, bfill, flags, foff, nfields, aid,
+                                      apos, s);
         else
-            last_pass<uint64_t, false>(src, sids, n, shift, P, counts, partials, bcounts, bpartials, flags,
-                                       foff, nfields, aid, apos, s);
+            last_pass<uint64_t, false>(src, sids, n, shift, P, counts, partials, bfill, flags, foff, nfields,
+                                       aid, apos, s);
         if (P.fine) {
             uint32_t *fid = (uint32_t *)keys[(p - 1) & 1];
             int32_t *fpos = (int32_t *)ids[(p - 1) & 1];
             const dim3 cgrid((unsigned)P.nchunks);
-            hipLaunchKernelGGL(k_fine_hist, cgrid, dim3(kThreads), 0, s, aid, n, P.fshift, P.flog, P.qlog,
-                               P.nchunks, counts);
-            exclusive_scan<uint32_t>(counts, P.nchunks << P.flog, partials, s);
             hipLaunchKernelGGL(k_fine_scatter, cgrid, dim3(kThreads), 0, s, aid, apos, n, P.fshift, P.flog,
-                               P.qlog, P.nchunks, counts, fid, fpos);
+                               P.qlog, P.nchunks, wfill, fid, fpos);
             aid = fid;
             apos = fpos;
         }
