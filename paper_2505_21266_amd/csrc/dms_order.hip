@@ -466,18 +466,15 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
     __shared__ int64_t fo[kField ? kFieldPassFields + 1 : 1];
     constexpr int kW = kThr / kWave, kT = kThr * kItems;
     __shared__ uint16_t dwh[kW][kRadix];
-    __shared__ uint16_t bwh[kW][kRadix];
+    __shared__ uint32_t bcnt[kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t bstart[kRadix];
     __shared__ uint32_t bbase[kRadix];
     __shared__ Staging<uint32_t, int32_t, kThr> S;
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    for (int i = tid; i < kW * kRadix; i += kThr) {
-        (&dwh[0][0])[i] = 0;
-        (&bwh[0][0])[i] = 0;
-    }
-    zero_masks(S);
+    for (int i = tid; i < kW * kRadix; i += kThr) (&dwh[0][0])[i] = 0;
+    if (tid < kRadix) bcnt[tid] = 0;
     if constexpr (kField) load_field_offsets(fo, foff, nfields);
     __syncthreads();
 
@@ -485,9 +482,12 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
     const int64_t t0 = tile * kT;
     const int count = tile_count<kT>(n, tile);
     if (count == 0) return;  // block-uniform
-    // per item after the ranking: the id and, packed, its digit rank and its
-    // bucket rank inside the wave (each below 16 x 64 = 2^10) and its digit;
-    // batches also keep the field
+    // per item after the ranking: the id and, packed, its digit rank inside
+    // the wave (below 16 x 64 = 2^10), its digit and its slot among the
+    // tile's pairs of its bucket (below 2^13); batches also keep the field.
+    // The digit ranks must be stable (they give the sorted position); the
+    // bucket slots need not be (the inversion places pairs by id), so they
+    // come from one LDS atomic per item.
     uint32_t id[kItems], pk[kItems];
     uint32_t fld[sizeof(K) == 8 || kField ? kItems : 1];
     {
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
             // spans few fields: ballots match it faster than the LDS masks,
             // which serve the random id buckets
             const uint32_t rd = wave_rank<false>(d, valid, dwh[wave], S.mk[wave]);
-            const uint32_t rb = wave_rank<true>((id[k] >> bshift) & (kRadix - 1), valid, bwh[wave], S.mk[wave]);
+            const uint32_t rb = valid ? atomicAdd(&bcnt[(id[k] >> bshift) & (kRadix - 1)], 1u) : 0u;
             // settled here: otherwise the compiler sinks the rank popcounts past
             // the barrier and keeps every item's two 64-bit lane masks alive
             pk[k] = settled(rd | d << 10 | rb << 18);
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
     {
         wave_prefix<kThr>(dwh);
         uint32_t total;
-        const uint32_t nb = wave_prefix<kThr>(bwh);  // the tile's pairs of bucket tid
+        const uint32_t nb = tid < kRadix ? bcnt[tid] : 0u;  // the tile's pairs of bucket tid
         const uint32_t start = block_exclusive_scan<uint32_t, kThr>(nb, &total);
         if (tid < kRadix) {
             bstart[tid] = start;
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
             } else if constexpr (sizeof(K) == 8) {
                 if (foff) base = foff[fld[k]];
             }
-            const uint32_t pos = bstart[b] + bwh[wave][b] + (pk[k] >> 18);
+            const uint32_t pos = bstart[b] + (pk[k] >> 18);
             if (pos < (uint32_t)kT) {
                 S.st.a[pos] = id[k];
                 S.st.b[pos] = (int32_t)(g - base);
@@ -574,50 +574,49 @@ __global__ __launch_bounds__(kThreads) void k_fine_scatter(const uint32_t *in_id
                                                            int64_t nchunks, uint32_t *wfill,
                                                            uint32_t *out_id, int32_t *out_pos)
 {
-    __shared__ uint32_t wh[kWaves][kRadix];
+    __shared__ uint32_t cnt[kRadix];
     __shared__ uint32_t dstart[kRadix];
     __shared__ uint32_t gbase[kRadix];
-    __shared__ Staging<uint32_t, int32_t> S;
+    __shared__ uint32_t sid[kTile];
+    __shared__ int32_t spos[kTile];
 
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    for (int i = tid; i < kWaves * kRadix; i += kThreads) (&wh[0][0])[i] = 0;
-    zero_masks(S);
+    if (tid < kRadix) cnt[tid] = 0;
     __syncthreads();
     const int64_t c = tile_of_block(nchunks);
     const int64_t t0 = c * kTile;
     const int count = tile_count(n, c);
-    const uint32_t fmask = (1u << flog) - 1u;
-    uint32_t id[kItems], r[kItems];
-    int32_t pos[kItems];
     if (count == 0) return;  // block-uniform
+    const uint32_t fmask = (1u << flog) - 1u;
+    uint32_t id[kItems], slot[kItems];
+    int32_t pos[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {  // unconditional loads (count >= 1)
         const int64_t at = item_at(t0, local_index(wave, k, lane), count - 1);
         id[k] = in_id[at];
         pos[k] = in_pos[at];
     }
+    // the order inside a window is free: a slot per item from one LDS atomic
 #pragma unroll
     for (int k = 0; k < kItems; ++k)
-        r[k] = wave_rank<false>((id[k] >> fshift) & fmask, local_index(wave, k, lane) < count, wh[wave],
-                               S.mk[wave]);
+        slot[k] = local_index(wave, k, lane) < count ? atomicAdd(&cnt[(id[k] >> fshift) & fmask], 1u) : 0u;
     __syncthreads();
     {
         uint32_t total;
-        const uint32_t nw = wave_prefix(wh);  // the chunk's pairs of window digit tid
+        const uint32_t nw = tid <= (int)fmask ? cnt[tid] : 0u;  // the chunk's pairs of window digit tid
         const uint32_t start = block_exclusive_scan<uint32_t>(nw, &total);
         dstart[tid] = start;
         const int64_t w = ((c >> qlog) << flog) | tid;
-        gbase[tid] = (tid <= (int)fmask && nw) ? (uint32_t)(w << fshift) + atomicAdd(&wfill[w], nw) - start : 0u;
+        gbase[tid] = nw ? (uint32_t)(w << fshift) + atomicAdd(&wfill[w], nw) - start : 0u;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         if (local_index(wave, k, lane) < count) {
-            const uint32_t d = (id[k] >> fshift) & fmask;
-            const uint32_t at = dstart[d] + wh[wave][d] + r[k];
+            const uint32_t at = dstart[(id[k] >> fshift) & fmask] + slot[k];
             if (at < (uint32_t)kTile) {
-                S.st.a[at] = id[k];
-                S.st.b[at] = pos[k];
+                sid[at] = id[k];
+                spos[at] = pos[k];
             }
         }
     }
@@ -626,11 +625,11 @@ __global__ __launch_bounds__(kThreads) void k_fine_scatter(const uint32_t *in_id
     for (int j = 0; j < kItems; ++j) {
         const int p = tid + j * kThreads;
         if (p < count) {
-            const uint32_t who = S.st.a[p];
+            const uint32_t who = sid[p];
             const uint32_t dst = gbase[(who >> fshift) & fmask] + (uint32_t)p;
             if ((int64_t)dst < n) {
                 out_id[dst] = who;
-                out_pos[dst] = S.st.b[p];
+                out_pos[dst] = spos[p];
             }
         }
     }
