@@ -568,11 +568,12 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
 // Level 1: a partition of each chunk of a coarse bucket by the fine digit
 // into the windows of ids.  As in level 0, a chunk's run for window w is
 // placed by one atomic add on the window's fill counter (wfill, zeroed
-// beforehand; window w starts at position w << fshift).
+// beforehand; window w starts at position w << fshift).  The ids are written
+// relative to their window (fshift <= 16 bits), 2 bytes instead of 4.
 __global__ __launch_bounds__(kThreads) void k_fine_scatter(const uint32_t *in_id, const int32_t *in_pos,
                                                            int64_t n, int fshift, int flog, int qlog,
                                                            int64_t nchunks, uint32_t *wfill,
-                                                           uint32_t *out_id, int32_t *out_pos)
+                                                           uint16_t *out_id, int32_t *out_pos)
 {
     __shared__ uint32_t cnt[kRadix];
     __shared__ uint32_t dstart[kRadix];
@@ -628,7 +629,7 @@ __global__ __launch_bounds__(kThreads) void k_fine_scatter(const uint32_t *in_id
             const uint32_t who = sid[p];
             const uint32_t dst = gbase[(who >> fshift) & fmask] + (uint32_t)p;
             if ((int64_t)dst < n) {
-                out_id[dst] = who;
+                out_id[dst] = (uint16_t)(who & ((1u << fshift) - 1u));  // the id within its window
                 out_pos[dst] = spos[p];
             }
         }
@@ -640,8 +641,10 @@ __global__ __launch_bounds__(kThreads) void k_fine_scatter(const uint32_t *in_id
 constexpr int kInvThreads = 1024;
 constexpr int kInvUnroll = 4;
 
-template <int kWinLog>
-__global__ __launch_bounds__(kInvThreads) void k_invert_window(const uint32_t *__restrict__ pair_id,
+// ID: uint32_t ids (windows straight from the coarse buckets), or uint16_t
+// ids relative to the window's first id (written by the fine level).
+template <int kWinLog, typename ID>
+__global__ __launch_bounds__(kInvThreads) void k_invert_window(const ID *__restrict__ pair_id,
                                                                const int32_t *__restrict__ pair_pos,
                                                                int64_t n, int wshift,
                                                                int32_t *__restrict__ order)
@@ -652,21 +655,19 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_window(const uint32_t *_
     const int64_t left = n - base;
     const int cnt = left < (1ll << wshift) ? (int)left : (1 << wshift);
     for (int i0 = 0; i0 < cnt; i0 += kInvThreads * kInvUnroll) {
-        uint32_t v[kInvUnroll];
+        int64_t off[kInvUnroll];
         int32_t r[kInvUnroll];
 #pragma unroll
         for (int u = 0; u < kInvUnroll; ++u) {  // unconditional loads (cnt >= 1)
             const int i = i0 + u * kInvThreads + (int)threadIdx.x;
             const int64_t at = base + (i < cnt ? i : cnt - 1);
-            v[u] = pair_id[at];
+            const int64_t v = (int64_t)pair_id[at];
             r[u] = pair_pos[at];
-            if (i >= cnt) v[u] = 0xffffffffu;
+            off[u] = i >= cnt ? -1 : (sizeof(ID) == 2 ? v : v - base);
         }
 #pragma unroll
-        for (int u = 0; u < kInvUnroll; ++u) {
-            const int64_t off = (int64_t)v[u] - base;
-            if (off >= 0 && off < cnt) win[off] = r[u];
-        }
+        for (int u = 0; u < kInvUnroll; ++u)
+            if (off[u] >= 0 && off[u] < cnt) win[off[u]] = r[u];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < cnt; i += kInvThreads) order[base + i] = win[i];
@@ -824,24 +825,28 @@ int run_order(const void *values, int64_t n, int passes, int32_t *order, char *w
         else
             last_pass<uint64_t, false>(src, sids, n, shift, P, counts, partials, bfill, flags, foff, nfields,
                                        aid, apos, s);
+        const int64_t nwin = (n + (1ll << P.wshift) - 1) >> P.wshift;
+        if (P.wshift > kMaxWinLog + 1) return DMS_E_SIZE;
         if (P.fine) {
-            uint32_t *fid = (uint32_t *)keys[(p - 1) & 1];
+            uint16_t *fid = (uint16_t *)keys[(p - 1) & 1];
             int32_t *fpos = (int32_t *)ids[(p - 1) & 1];
             const dim3 cgrid((unsigned)P.nchunks);
             hipLaunchKernelGGL(k_fine_scatter, cgrid, dim3(kThreads), 0, s, aid, apos, n, P.fshift, P.flog,
                                P.qlog, P.nchunks, wfill, fid, fpos);
-            aid = fid;
-            apos = fpos;
+            if (P.wshift <= kMaxWinLog)
+                hipLaunchKernelGGL((k_invert_window<kMaxWinLog, uint16_t>), dim3((unsigned)nwin),
+                                   dim3(kInvThreads), 0, s, fid, fpos, n, P.wshift, order);
+            else
+                hipLaunchKernelGGL((k_invert_window<kMaxWinLog + 1, uint16_t>), dim3((unsigned)nwin),
+                                   dim3(kInvThreads), 0, s, fid, fpos, n, P.wshift, order);
+        } else {
+            if (P.wshift <= kMaxWinLog)
+                hipLaunchKernelGGL((k_invert_window<kMaxWinLog, uint32_t>), dim3((unsigned)nwin),
+                                   dim3(kInvThreads), 0, s, aid, apos, n, P.wshift, order);
+            else
+                hipLaunchKernelGGL((k_invert_window<kMaxWinLog + 1, uint32_t>), dim3((unsigned)nwin),
+                                   dim3(kInvThreads), 0, s, aid, apos, n, P.wshift, order);
         }
-        const int64_t nwin = (n + (1ll << P.wshift) - 1) >> P.wshift;
-        if (P.wshift <= kMaxWinLog)
-            hipLaunchKernelGGL(k_invert_window<kMaxWinLog>, dim3((unsigned)nwin), dim3(kInvThreads), 0,
-                               s, aid, apos, n, P.wshift, order);
-        else if (P.wshift == kMaxWinLog + 1)
-            hipLaunchKernelGGL(k_invert_window<kMaxWinLog + 1>, dim3((unsigned)nwin),
-                               dim3(kInvThreads), 0, s, aid, apos, n, P.wshift, order);
-        else
-            return DMS_E_SIZE;
     }
     return launch_status();
 }
