@@ -116,20 +116,26 @@ __device__ __forceinline__ int tile_count(int64_t n, int64_t tile)
     return left <= 0 ? 0 : (left < kT ? (int)left : kT);
 }
 
-// Histogram update for one item per lane (counts only, no ranks), one LDS
-// atomic instruction: the lanes holding the first active lane's digit are
-// counted by a ballot and added once, by that lane; the others add 1 each.
-// Skewed digits (the high bytes of a smooth field) thus cost few same-address
-// atomics.
-__device__ __forceinline__ void hist_add(uint32_t *h, uint32_t d, bool valid)
+// Histogram counters of a block: kCopies copies of the kRadix counts, lane l
+// adding into copy l % kCopies, so that at most kWave / kCopies lanes of one
+// LDS atomic instruction hit the same counter.  A digit that takes few values
+// in random order (the top byte after the lower bytes have been sorted) would
+// otherwise serialise most of a wave on one or two addresses.  Rows are
+// padded by one word so that a digit's copies sit in different banks.
+constexpr int kCopies = 16;
+using HistRows = uint32_t[kCopies][kRadix + 1];
+
+// One item per lane; a wave whose items share one digit adds them with one
+// atomic.
+__device__ __forceinline__ void hist_add(HistRows &h, uint32_t d, bool valid)
 {
     const uint64_t act = __ballot(valid);
-    if (act == 0) return;
-    const int leader = (int)__builtin_ctzll(act);
-    const uint32_t d0 = __builtin_amdgcn_readlane(d, leader);
-    const uint64_t same = __ballot(valid && d == d0);
-    const bool lead = lane_id() == leader;
-    if (valid && (d != d0 || lead)) atomicAdd(&h[d], lead ? (uint32_t)__popcll(same) : 1u);
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(valid ? d : 0xffffffffu);
+    if (__ballot(valid && d == d0) == act) {
+        if (act != 0 && lane_id() == (int)__builtin_ctzll(act)) atomicAdd(&h[0][d0], (uint32_t)__popcll(act));
+        return;
+    }
+    if (valid) atomicAdd(&h[lane_id() & (kCopies - 1)][d], 1u);
 }
 
 // Element type read by a pass: the caller's values in the first pass, the
@@ -171,8 +177,7 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
                                                         const int64_t *foff, int nfields)
 {
     __shared__ int64_t fo[kField ? kFieldPassFields + 1 : 1];
-    constexpr int kW = kThr / kWave;
-    __shared__ uint32_t hist[kW][kRadix];
+    __shared__ HistRows hist;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int64_t tile = tile_of_block(ntiles);
     const int64_t t0 = tile * (kThr * kItems);
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
 #pragma unroll
         for (int k = 0; k < kItems; ++k) bid[k] = ids[item_at(t0, local_index(wave, k, lane), last)];
     }
-    for (int i = tid; i < kW * kRadix; i += kThr) (&hist[0][0])[i] = 0;
+    for (int i = tid; i < kCopies * (kRadix + 1); i += kThr) (&hist[0][0])[i] = 0;
     if constexpr (kField) load_field_offsets(fo, foff, nfields);
     __syncthreads();
     bool nan_any = false;
@@ -205,14 +210,14 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
             nan_any |= valid && nan;
             d = (uint32_t)(key >> shift) & (kRadix - 1);
         }
-        hist_add(hist[wave], d, valid);
+        hist_add(hist, d, valid);
     }
     __syncthreads();
     if (kFirst && __ballot(nan_any) && lane == 0) atomicOr(flags, (uint32_t)DMS_FLAG_NAN);
     if (tid >= kRadix) return;  // a thread per digit
     uint32_t tot = 0;
 #pragma unroll
-    for (int w = 0; w < kW; ++w) tot += hist[w][tid];
+    for (int c = 0; c < kCopies; ++c) tot += hist[c][tid];
     counts[(int64_t)tid * ntiles + tile] = tot;  // digit-major, tiles in tile order
 }
 
