@@ -287,14 +287,44 @@ __device__ __forceinline__ uint32_t wave_prefix(CT (*wh)[kRadix])
 // the field index above the value key.
 // LDS staging of a tile; the digit masks of the ranking phase live in the
 // same bytes (the phases are separated by a barrier).
+// A and B of at most 4 bytes each are staged packed in one 64-bit word (a in
+// the low half): one LDS write and one read per item instead of two each.
 template <typename A, typename B, int kThr = kThreads>
 union Staging {
     struct {
         A a[kThr * kItems];
         B b[kThr * kItems];
     } st;
+    uint64_t ab[kThr * kItems];
     uint64_t mk[kThr / kWave][kRadix];
 };
+
+template <typename A, typename B>
+constexpr bool kPacked = sizeof(A) <= 4 && sizeof(B) <= 4;
+
+template <typename A, typename B, int kThr>
+__device__ __forceinline__ void stage_put(Staging<A, B, kThr> &S, uint32_t pos, A a, B b)
+{
+    if constexpr (kPacked<A, B>) {
+        S.ab[pos] = (uint64_t)(uint32_t)b << 32 | (uint64_t)a;
+    } else {
+        S.st.a[pos] = a;
+        S.st.b[pos] = b;
+    }
+}
+
+template <typename A, typename B, int kThr>
+__device__ __forceinline__ void stage_get(const Staging<A, B, kThr> &S, int p, A &a, B &b)
+{
+    if constexpr (kPacked<A, B>) {
+        const uint64_t v = S.ab[p];
+        a = (A)v;
+        b = (B)(uint32_t)(v >> 32);
+    } else {
+        a = S.st.a[p];
+        b = S.st.b[p];
+    }
+}
 
 template <typename A, typename B, int kThr>
 __device__ __forceinline__ void zero_masks(Staging<A, B, kThr> &S)
@@ -313,7 +343,6 @@ __global__ __launch_bounds__(kThr) void k_scatter(const void *src, const uint32_
 {
     constexpr int kW = kThr / kWave;
     __shared__ uint32_t whist[kW][kRadix];
-    __shared__ uint32_t digit_start[kRadix];
     __shared__ uint32_t gbase[kRadix];
     __shared__ Staging<K, uint32_t, kThr> S;
 
@@ -367,10 +396,13 @@ __global__ __launch_bounds__(kThr) void k_scatter(const void *src, const uint32_
     {
         uint32_t total;
         const uint32_t start = block_exclusive_scan<uint32_t, kThr>(wave_prefix<kThr>(whist), &total);
-        // global position of the tile's element at local position p of digit d:
-        // gbase[d] + p (gbase holds the scanned offset minus the local start)
+        // whist[w][d] becomes the tile position of wave w's first item of
+        // digit d; the global position of the tile's element at local
+        // position p of digit d is gbase[d] + p (gbase holds the scanned
+        // offset minus the local start)
         if (tid < kRadix) {
-            digit_start[tid] = start;
+#pragma unroll
+            for (int w = 0; w < kW; ++w) whist[w][tid] += start;
             gbase[tid] = offsets[(int64_t)tid * ntiles + tile] - start;
         }
     }
@@ -379,9 +411,7 @@ __global__ __launch_bounds__(kThr) void k_scatter(const void *src, const uint32_
     for (int k = 0; k < kItems; ++k) {
         if (local_index(wave, k, lane) < count) {
             const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-            const uint32_t pos = digit_start[d] + whist[wave][d] + rank[k];
-            S.st.a[pos] = key[k];
-            S.st.b[pos] = id[k];
+            stage_put(S, whist[wave][d] + rank[k], key[k], id[k]);
         }
     }
     __syncthreads();
@@ -389,12 +419,14 @@ __global__ __launch_bounds__(kThr) void k_scatter(const void *src, const uint32_
     for (int j = 0; j < kItems; ++j) {
         const int p = tid + j * kThr;
         if (p < count) {
-            const K kk = S.st.a[p];
+            K kk;
+            uint32_t who;
+            stage_get(S, p, kk, who);
             const uint32_t g = gbase[(uint32_t)(kk >> shift) & (kRadix - 1)] + (uint32_t)p;
             // the ranks make g < n; the guard keeps any breach of that in bounds
             if ((int64_t)g < n) {
                 if constexpr (!std::is_same_v<KD, NoKey>) ((KD *)dst_keys)[g] = (KD)(kk >> strip);
-                dst_ids[g] = S.st.b[p];
+                dst_ids[g] = who;
             }
         }
     }
@@ -549,10 +581,7 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
                 if (foff) base = foff[fld[k]];
             }
             const uint32_t pos = bstart[b] + (pk[k] >> 18);
-            if (pos < (uint32_t)kT) {
-                S.st.a[pos] = id[k];
-                S.st.b[pos] = (int32_t)(g - base);
-            }
+            if (pos < (uint32_t)kT) stage_put(S, pos, id[k], (int32_t)(g - base));
         }
     }
     __syncthreads();
@@ -560,11 +589,13 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
     for (int j = 0; j < kItems; ++j) {
         const int p = tid + j * kThr;
         if (p < count) {
-            const uint32_t who = S.st.a[p];
+            uint32_t who;
+            int32_t at;
+            stage_get(S, p, who, at);
             const uint32_t dst = bbase[(who >> bshift) & (kRadix - 1)] + (uint32_t)p;
             if ((int64_t)dst < n) {
                 pair_id[dst] = who;
-                pair_pos[dst] = S.st.b[p];
+                pair_pos[dst] = at;
             }
         }
     }
