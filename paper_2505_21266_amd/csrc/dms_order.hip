@@ -502,9 +502,11 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
 {
     __shared__ int64_t fo[kField ? kFieldPassFields + 1 : 1];
     constexpr int kW = kThr / kWave, kT = kThr * kItems;
-    __shared__ uint16_t dwh[kW][kRadix];
+    // dwh: per-wave digit counts while ranking, then the final position of
+    // wave w's first item of digit d (for a field pass, relative to the
+    // field's first vertex)
+    __shared__ uint32_t dwh[kW][kRadix];
     __shared__ uint32_t bcnt[kRadix];
-    __shared__ uint32_t gbase[kRadix];
     __shared__ uint32_t bstart[kRadix];
     __shared__ uint32_t bbase[kRadix];
     __shared__ Staging<uint32_t, int32_t, kThr> S;
@@ -521,12 +523,13 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
     if (count == 0) return;  // block-uniform
     // per item after the ranking: the id and, packed, its digit rank inside
     // the wave (below 16 x 64 = 2^10), its digit and its slot among the
-    // tile's pairs of its bucket (below 2^13); batches also keep the field.
+    // tile's pairs of its bucket (below 2^13); batches of 8-byte keys also
+    // keep the field.
     // The digit ranks must be stable (they give the sorted position); the
     // bucket slots need not be (the inversion places pairs by id), so they
     // come from one LDS atomic per item.
     uint32_t id[kItems], pk[kItems];
-    uint32_t fld[sizeof(K) == 8 || kField ? kItems : 1];
+    uint32_t fld[sizeof(K) == 8 ? kItems : 1];
     {
         K key[kItems];
 #pragma unroll
@@ -551,8 +554,7 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
             // settled here: otherwise the compiler sinks the rank popcounts past
             // the barrier and keeps every item's two 64-bit lane masks alive
             pk[k] = settled(rd | d << 10 | rb << 18);
-            if constexpr (kField) fld[k] = d;
-            else if constexpr (sizeof(K) == 8) fld[k] = (uint32_t)(key[k] >> 32);
+            if constexpr (!kField && sizeof(K) == 8) fld[k] = (uint32_t)(key[k] >> 32);
         }
     }
     __syncthreads();
@@ -563,7 +565,10 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
         const uint32_t start = block_exclusive_scan<uint32_t, kThr>(nb, &total);
         if (tid < kRadix) {
             bstart[tid] = start;
-            gbase[tid] = offsets[(int64_t)tid * ntiles + tile];
+            uint32_t gb = offsets[(int64_t)tid * ntiles + tile];
+            if constexpr (kField) gb -= tid <= nfields ? (uint32_t)fo[tid] : 0u;  // the digit is the field
+#pragma unroll
+            for (int w = 0; w < kW; ++w) dwh[w][tid] += gb;
             bbase[tid] = nb ? ((uint32_t)tid << bshift) + atomicAdd(&bfill[tid], nb) - start : 0u;
         }
     }
@@ -573,15 +578,12 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
         if (local_index(wave, k, lane) < count) {
             const uint32_t d = (pk[k] >> 10) & (kRadix - 1);
             const uint32_t b = (id[k] >> bshift) & (kRadix - 1);
-            const int64_t g = (int64_t)gbase[d] + dwh[wave][d] + (pk[k] & 1023u);
-            int64_t base = 0;
-            if constexpr (kField) {
-                base = fo[fld[k]];
-            } else if constexpr (sizeof(K) == 8) {
-                if (foff) base = foff[fld[k]];
+            int64_t g = (int64_t)(dwh[wave][d] + (pk[k] & 1023u));
+            if constexpr (!kField && sizeof(K) == 8) {
+                if (foff) g -= foff[fld[k]];
             }
             const uint32_t pos = bstart[b] + (pk[k] >> 18);
-            if (pos < (uint32_t)kT) stage_put(S, pos, id[k], (int32_t)(g - base));
+            if (pos < (uint32_t)kT) stage_put(S, pos, id[k], (int32_t)g);
         }
     }
     __syncthreads();
