@@ -187,61 +187,42 @@ __device__ __forceinline__ uint32_t low_of_ranks(uint64_t rank_of)
     return low;
 }
 
-__device__ __forceinline__ bool robins(uint64_t rank_of, int mmax, const SharedTables &T, uint4 &out);
+__device__ __forceinline__ bool robins(uint64_t rank_of, const SharedTables &T, uint4 &out);
 
 // The cell of S with the smallest key, as a one-bit set (S if S has at
 // most one cell), bit-sliced from the top rank plane down: keep the cells
-// without rank b when there are any.  mmax (uniform over the wave) bounds
-// the ranks, so the walk enters at plane mmax - 1 through a uniform switch.
-// (Stopping early once no lane of the wave has two candidates left cost
-// more in checks than it saved in planes.)
-__device__ __forceinline__ uint64_t smallest_by_key(uint64_t S, const uint64_t *nkp, int mmax)
+// without rank b when there are any.  All 14 planes are walked, as
+// straight-line code; planes at or above the lower-neighbour count are all
+// ones and change nothing.  (Entering the walk at the wave's largest lower
+// count instead, through a switch, cost a branch chain and register copies
+// in every step; instances for a few plane counts raised register pressure
+// into spills; stopping early once no lane has two candidates left cost more
+// in checks than it saved in planes.)
+__device__ __forceinline__ uint64_t smallest_by_key(uint64_t S, const uint64_t *nkp)
 {
-#define DMS_PLANE(B)                                                                                     \
-    do {                                                                                                 \
-        const uint64_t z = S & nkp[B];                                                                   \
-        S = z ? z : S;                                                                                   \
-    } while (0)
-    switch (mmax) {
-    default:
-    case 14: DMS_PLANE(13); [[fallthrough]];
-    case 13: DMS_PLANE(12); [[fallthrough]];
-    case 12: DMS_PLANE(11); [[fallthrough]];
-    case 11: DMS_PLANE(10); [[fallthrough]];
-    case 10: DMS_PLANE(9); [[fallthrough]];
-    case 9: DMS_PLANE(8); [[fallthrough]];
-    case 8: DMS_PLANE(7); [[fallthrough]];
-    case 7: DMS_PLANE(6); [[fallthrough]];
-    case 6: DMS_PLANE(5); [[fallthrough]];
-    case 5: DMS_PLANE(4); [[fallthrough]];
-    case 4: DMS_PLANE(3); [[fallthrough]];
-    case 3: DMS_PLANE(2); [[fallthrough]];
-    case 2: DMS_PLANE(1); [[fallthrough]];
-    case 1: DMS_PLANE(0); [[fallthrough]];
-    case 0: break;
+#pragma unroll
+    for (int b = 13; b >= 0; --b) {
+        const uint64_t z = S & nkp[b];
+        S = z ? z : S;
     }
-#undef DMS_PLANE
     return S;
 }
 
 // Robins' ProcessLowerStars for one vertex, from the orders of x and its 14
-// neighbours (kAbsent for neighbours outside the grid); mmax as in robins.
+// neighbours (kAbsent for neighbours outside the grid).
 // Returns whether L(x) holds a critical cell.
 template <typename C>
-__device__ __forceinline__ bool process_vertex(const C *o, C ox, int mmax, const SharedTables &T,
-                                               uint4 &out)
+__device__ __forceinline__ bool process_vertex(const C *o, C ox, const SharedTables &T, uint4 &out)
 {
     const uint32_t low = lower_mask(o, ox);
     if (low == 0) {  // L(x) = {x}: x is critical
         out = make_uint4(0, 0, 0, 0);
         return true;
     }
-    return robins(lower_ranks(o, low), mmax, T, out);
+    return robins(lower_ranks(o, low), T, out);
 }
 
 // The pairing itself, from the ranks of the lower neighbours (lower_ranks).
-// mmax is an upper bound, uniform over the wave, of the number of lower
-// neighbours.
 //
 // The two priority queues of Robins' formulation are not stored: at any time
 // the one-facet queue, minus entries that have meanwhile lost their last
@@ -255,7 +236,7 @@ __device__ __forceinline__ bool process_vertex(const C *o, C ox, int mmax, const
 // plane b holds the cells that contain the neighbour of rank b, and the key
 // of a cell is the integer with those bits (Section 2.1 comparison).
 // Returns whether some cell of L(x) ends critical.
-__device__ __forceinline__ bool robins(uint64_t rank_of, int mmax, const SharedTables &T, uint4 &out)
+__device__ __forceinline__ bool robins(uint64_t rank_of, const SharedTables &T, uint4 &out)
 {
     const uint32_t low = low_of_ranks(rank_of);
     if (low == 0) {
@@ -294,7 +275,7 @@ __device__ __forceinline__ bool robins(uint64_t rank_of, int mmax, const SharedT
         const uint64_t one = ftq & cnt.b0 & ~cnt.b1;
         uint64_t S = one ? one : (ftq & ~cnt.b0 & ~cnt.b1);
         if (S == 0 && fr == 0) break;
-        S = smallest_by_key(S, nkp, mmax);
+        S = smallest_by_key(S, nkp);
         const bool have_a = S != 0;
         const int a = have_a ? __ffsll((unsigned long long)S) - 1 : 0;
         if (one) {
@@ -737,13 +718,9 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
         if (nq == total) return;
         // the queue is full: pair the rest here (rare, so unsorted)
         const bool here = (uint32_t)tid >= nq && mine;
-        int mmax = here ? __popc(low) : 0;
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
-        mmax = __builtin_amdgcn_readfirstlane(mmax);
         if (here) {
             uint4 r;
-            const bool crit = robins(rk, mmax, sh.T, r);
+            const bool crit = robins(rk, sh.T, r);
             rec[ridx] = r;
             if (mark && crit) mark_critical(mark, ridx);
         }
@@ -782,14 +759,9 @@ __device__ __forceinline__ void gradient_tile(const void *__restrict__ field, in
         const int c = (tx + 1) + S::HX * ((ty + 1) + S::HY);
         C o[14], ox;
         gather_orders<Keys, GX, GY>(tile, c, o, ox);
-        const int m = active ? __popc(lower_mask(o, ox)) : 0;
-        int mmax = m;
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
-        mmax = __builtin_amdgcn_readfirstlane(mmax);
         if (active) {
             uint4 r;
-            const bool crit = process_vertex(o, ox, mmax, sh.T, r);
+            const bool crit = process_vertex(o, ox, sh.T, r);
             const int64_t ri = rbase + tx + w0 * ty;
             rec[ri] = r;
             if (mark && crit) mark_critical(mark, ri);
@@ -890,14 +862,9 @@ __global__ __launch_bounds__(kThreads) void k_gradient_queue(const uint4 *__rest
         uint4 e = make_uint4(0xffffffffu, 0x00ffffffu, 0u, 0u);  // no lower neighbour
         if (active) e = queue[start + perm[i]];
         const uint64_t rk = entry_ranks(e);
-        const int m = __popc(low_of_ranks(rk));
-        int mmax = m;
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
-        mmax = __builtin_amdgcn_readfirstlane(mmax);
         if (active) {
             uint4 r;
-            const bool crit = robins(rk, mmax, T, r);
+            const bool crit = robins(rk, T, r);
             const int64_t ri = entry_record(e);
             rec[ri] = r;
             if (mark && crit) mark_critical(mark, ri);
@@ -949,7 +916,7 @@ __global__ __launch_bounds__(kThreads) void k_regular_table()
             o[13 - lowm] = 100 + i;  // above x
         }
         uint4 r;
-        crit = process_vertex(o, 50, 14, T, r);
+        crit = process_vertex(o, 50, T, r);
         g_regular[idx] = r;
     }
     const uint64_t m = __ballot(crit);
@@ -993,7 +960,7 @@ __global__ __launch_bounds__(kThreads) void k_defect_table(uint4 *table)
                 o[((side >> i) & 1u) ? 13 - i : i] = (int32_t)rank[i];
             }
             if (kEight) o[j] = (int32_t)rank[7];
-            crit = process_vertex(o, 50, 14, T, r);
+            crit = process_vertex(o, 50, T, r);
         }
         table[idx] = r;
     }
