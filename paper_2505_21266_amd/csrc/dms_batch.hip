@@ -6,7 +6,7 @@
 // key (field index above the float32 value key), so each field's ranks are
 // its global positions minus the field's offset.  The gradient is one
 // launch over the (field, tile) list, a block per tile; the extraction one
-// pass over all records.  The first run records these launches into a hipGraph on a
+// pass over the records the gradient flagged in its critical mask.  The first run records these launches into a hipGraph on a
 // private capture stream; later runs with the same arguments replay it on the
 // caller's stream.  An autotuner picks the gradient tile shape per batch
 // (timed on the first run, remembered in an optional cache file).
@@ -79,14 +79,18 @@ void cache_store(const std::string &path, uint64_t sig, int variant)
 
 struct Ws {
     char *order, *crit, *grad;
+    uint32_t *mask;  // the critical mask: a bit per record
 };
+
+size_t mask_bytes(int64_t total) { return dms::align_up((size_t)((total + 31) / 32) * 4, 256); }
 
 Ws carve(const dms_batch *b, void *ws)
 {
     Ws w;
     w.order = (char *)ws;
     w.crit = w.order + dms::align_up(dms::order_batch_workspace_size(b->total), 256);
-    w.grad = w.crit + dms::align_up(dms::critical_batch_workspace_size(b->total, b->nfields), 256);
+    w.mask = (uint32_t *)(w.crit + dms::align_up(dms::critical_batch_workspace_size(b->total, b->nfields), 256));
+    w.grad = (char *)w.mask + mask_bytes(b->total);
     return w;
 }
 
@@ -108,14 +112,14 @@ int enqueue_all(dms_batch *b, const void *values, int32_t *order, uint32_t *rec,
     if (st) return st;
     st = dms::launch_gradient_batch(b->variant, order, b->d_fields, b->nfields, b->d_tiles[b->variant],
                                     b->d_tile_field[b->variant], b->tiles[b->variant], b->total, rec,
-                                    w.grad, s);
+                                    w.mask, w.grad, s);
     if (st) return st;
-    return dms::launch_critical_batch(rec, b->total, b->d_off, b->nfields, b->d_fields, crit, cap,
+    return dms::launch_critical_batch(rec, w.mask, b->total, b->d_off, b->nfields, b->d_fields, crit, cap,
                                       counts, offsets, w.crit, flags, s);
 }
 
 // Times each tile shape on the caller's data (the order must be ready).
-int autotune(dms_batch *b, const int32_t *order, uint32_t *rec, char *gws, hipStream_t s)
+int autotune(dms_batch *b, const int32_t *order, uint32_t *rec, const Ws &w, hipStream_t s)
 {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DMS_E_HIP;
@@ -127,7 +131,7 @@ int autotune(dms_batch *b, const int32_t *order, uint32_t *rec, char *gws, hipSt
             (void)hipEventRecord(e0, s);
             int st = dms::launch_gradient_batch(v, order, b->d_fields, b->nfields, b->d_tiles[v],
                                                 b->d_tile_field[v], b->tiles[v],
-                                                b->total, rec, gws, s);
+                                                b->total, rec, w.mask, w.grad, s);
             (void)hipEventRecord(e1, s);
             if (st) return st;
             if (hipEventSynchronize(e1) != hipSuccess) return DMS_E_HIP;
@@ -223,7 +227,7 @@ extern "C" size_t dms_batch_workspace_size(const dms_batch *b)
 {
     if (!b) return 0;
     return dms::align_up(dms::order_batch_workspace_size(b->total), 256) +
-           dms::align_up(dms::critical_batch_workspace_size(b->total, b->nfields), 256) +
+           dms::align_up(dms::critical_batch_workspace_size(b->total, b->nfields), 256) + mask_bytes(b->total) +
            dms::gradient_workspace_size(b->total);
 }
 
@@ -249,7 +253,7 @@ extern "C" int dms_batch_run(dms_batch *b, const void *values, int32_t *order, u
         int st = dms::launch_order_batch((const float *)values, b->total, b->d_off, b->nfields, order,
                                          w.order, dev_flags, s);
         if (st) return st;
-        st = autotune(b, order, rec, w.grad, s);
+        st = autotune(b, order, rec, w, s);
         if (st) return st;
         b->tuned = true;
         destroy_graph(b);

@@ -32,14 +32,6 @@ struct Fields {
     uint64_t lo, hi;
 };
 
-__device__ __forceinline__ uint32_t edge_field(uint64_t lo, int e) { return (uint32_t)(lo >> (4 * e)) & 15u; }
-
-__device__ __forceinline__ uint32_t tri_field(uint64_t lo, uint64_t hi, int t)
-{
-    const int b = 56 + 2 * t;
-    return (uint32_t)((b < 64 ? lo >> b : hi >> (b - 64)) & 3u);
-}
-
 // L(x) edge mask from the edge fields: bit e set iff edge field e is non-zero
 // (nibble-wise OR, then the 14 nibble bits compressed into 14 adjacent bits)
 __device__ __forceinline__ uint32_t lower_edges(uint64_t lo)
@@ -616,27 +608,39 @@ constexpr int kWavesPerBlock = kThreads / kWave;
 static_assert(kWave == 64 && kTileWords == 2 * kRows && kTilesPerWave == 2, "one mask word per lane");
 
 // The wave's flagged records: word = mask word `lane` of the wave's tiles.
-// Returns their number; when it is at most kWave, rel (of lane j < number)
-// is the j-th flagged record's position from the first tile's start.
-__device__ __forceinline__ uint32_t list_flagged(uint32_t word, int lane, uint32_t &rel)
+// flag_scan returns their number and sets inc (inclusive scan of the words'
+// bit counts over the lanes); flag_at gives the j-th flagged record's
+// position from the first tile's start (j below the number).
+__device__ __forceinline__ uint32_t flag_scan(uint32_t word, int lane, uint32_t &inc)
 {
-    const uint32_t pc = (uint32_t)__popc(word);
-    uint32_t inc = pc;
+    inc = (uint32_t)__popc(word);
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
         const uint32_t t = __shfl_up(inc, off);
         if (lane >= off) inc += t;
     }
-    const uint32_t total = __shfl(inc, kWave - 1);
-    // the word holding flagged record j = lane: the first w with inc[w] > j
-    const uint32_t j = (uint32_t)lane;
+    return __shfl(inc, kWave - 1);
+}
+
+__device__ __forceinline__ uint32_t flag_at(uint32_t word, uint32_t inc, uint32_t j)
+{
+    // the word holding flagged record j: the first w with inc[w] > j
     int w = 0;
 #pragma unroll
     for (int step = kWave / 2; step > 0; step >>= 1)
         if (__shfl(inc, w + step - 1) <= j) w += step;
     const uint32_t ww = __shfl(word, w);
     const uint32_t before = __shfl(inc, w) - (uint32_t)__popc(ww);
-    rel = (uint32_t)w * 32u + select_bit(ww, j - before);
+    return (uint32_t)w * 32u + select_bit(ww, j - before);
+}
+
+// Their number; when it is at most kWave, rel (of lane j < number) is the
+// j-th flagged record's position.
+__device__ __forceinline__ uint32_t list_flagged(uint32_t word, int lane, uint32_t &rel)
+{
+    uint32_t inc;
+    const uint32_t total = flag_scan(word, lane, inc);
+    rel = flag_at(word, inc, (uint32_t)lane < total ? (uint32_t)lane : 0u);
     return total;
 }
 
@@ -772,29 +776,18 @@ __global__ void k_crit_finish(const uint64_t *offs, int64_t ntiles, int64_t *cou
 }
 
 
-// Field of record r of a batch (so: the fields' first records, in LDS).
-__device__ __forceinline__ int record_field(const int64_t *so, int nfields, int64_t r)
-{
-    int lo = 0, hi = nfields - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (so[mid] <= r) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Batched fill: records of whole fields concatenated; codes carry the
-// field-local vertex id.  A wave takes kTilesPerWave consecutive tiles and
-// walks each in rows of kWave consecutive records (one coalesced load per
-// row, the next row's load in flight while a row is written; a row's codes
-// leave as one run at the running offset).  Tiles whose scanned counts are
-// all zero are skipped unread, rows without critical cells cost no scan.
-constexpr int kBatchTilesPerWave = 8;
-
+// Batched fill from the critical mask: records of whole fields
+// concatenated; codes carry the field-local vertex id.  A wave takes
+// kTilesPerWave consecutive tiles (one mask word per lane) and their flagged
+// records kWave at a time, in record order (lane j the chunk's j-th), so that
+// every decode serves a flagged record; a chunk's codes leave as one run at
+// the running offset.  Most records of a noise field hold no critical cell,
+// but most rows of 64 records hold one, so walking rows would decode them all.
 __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
-    const uint4 *__restrict__ rec, int64_t nbox, const uint64_t *__restrict__ offs, int64_t ntiles,
-    const int64_t *__restrict__ foff, int nfields, int64_t *crit0, int64_t *crit1, int64_t *crit2,
-    int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2, int64_t cap3)
+    const uint4 *__restrict__ rec, const uint32_t *__restrict__ mask, int64_t nbox,
+    const uint64_t *__restrict__ offs, int64_t ntiles, const int64_t *__restrict__ foff, int nfields,
+    int64_t *crit0, int64_t *crit1, int64_t *crit2, int64_t *crit3, int64_t cap0, int64_t cap1, int64_t cap2,
+    int64_t cap3)
 {
     __shared__ int64_t so[kMaxBatchFields + 1];
     __shared__ DecodeTables D;
@@ -804,44 +797,42 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_batch(
     const int lane = lane_id();
     const int64_t tile0 =
         (int64_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave)) *
-        kBatchTilesPerWave;
+        kTilesPerWave;
     if (tile0 >= ntiles) return;
+    const int64_t wi = tile0 * kTileWords + lane;
+    const uint32_t word = wi < (nbox + 31) / 32 ? mask[wi] : 0u;
+    if (!__ballot(word != 0u)) return;
     uint64_t at[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) at[d] = offs[(int64_t)d * ntiles + tile0] - offs[(int64_t)d * ntiles];
-    // field of the wave's first record (uniform); later rows move it forward
+    const int64_t r0 = tile0 * kTileRecs;
+    // field of the wave's first record (uniform); a lane's record lies in it
+    // or in a later field
     int f0 = 0;
     for (int step = 1 << 10; step > 0; step >>= 1)
-        if (f0 + step < nfields && so[f0 + step] <= tile0 * kTileRecs) f0 += step;
-    for (int t = 0; t < kBatchTilesPerWave; ++t) {
-        const int64_t tile = tile0 + t;
-        if (tile >= ntiles) break;
-        uint64_t any = 0;  // offs has 4 ntiles + 1 entries: tile + 1 is always in range
-#pragma unroll
-        for (int d = 0; d < 4; ++d) any |= offs[(int64_t)d * ntiles + tile + 1] - offs[(int64_t)d * ntiles + tile];
-        if (any == 0) continue;
+        if (f0 + step < nfields && so[f0 + step] <= r0) f0 += step;
+    uint32_t inc;
+    const uint32_t total = flag_scan(word, lane, inc);
 #pragma unroll 1
-        for (int k = 0; k < kRows; ++k) {
-            const int64_t row = tile * kTileRecs + (int64_t)k * kWave;
-            if (row >= nbox) break;
-            const int64_t r = row + lane;
-            uint64_t pk = 0;
-            uint32_t ce = 0, cq = 0;
-            uint64_t ct = 0;
-            if (r < nbox) {
-                const uint4 w = rec[r];
-                pk = decode_record((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32),
-                                   D, ce, ct, cq);
-            }
-            if (!__ballot(pk != 0)) continue;
-            while (f0 + 1 < nfields && so[f0 + 1] <= row) ++f0;  // uniform
-            int f = f0;
-            while (f + 1 < nfields && so[f + 1] <= r) ++f;  // fields shorter than a row
-            const uint64_t tot = emit_codes(ce, ct, cq, r - so[f], pk, at, crit0, crit1, crit2, crit3, cap0, cap1,
-                                            cap2, cap3);
-#pragma unroll
-            for (int d = 0; d < 4; ++d) at[d] += lane16(tot, d);
+    for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
+        const uint32_t j = c0 + (uint32_t)lane;
+        const bool take = j < total;
+        const int64_t r = r0 + flag_at(word, inc, take ? j : c0);
+        uint64_t pk = 0;
+        uint32_t ce = 0, cq = 0;
+        uint64_t ct = 0;
+        int f = f0;
+        if (take && r < nbox) {
+            const uint4 w = rec[r];
+            pk = decode_record((uint64_t)w.x | ((uint64_t)w.y << 32), (uint64_t)w.z | ((uint64_t)w.w << 32), D,
+                               ce, ct, cq);
+            while (f + 1 < nfields && so[f + 1] <= r) ++f;
         }
+        if (!__ballot(pk != 0)) continue;
+        const uint64_t tot =
+            emit_codes(ce, ct, cq, r - so[f], pk, at, crit0, crit1, crit2, crit3, cap0, cap1, cap2, cap3);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) at[d] += lane16(tot, d);
     }
 }
 
@@ -993,24 +984,24 @@ size_t critical_batch_workspace_size(int64_t n, int nfields)
     return crit_layout((n + kTileRecs - 1) / kTileRecs).total;
 }
 
-int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, int nfields,
-                          const BatchField *fields, int64_t *const crit[4], const int64_t cap[4],
-                          int64_t *counts, int64_t *offsets, char *ws, uint32_t *flags,
-                          hipStream_t s)
+int launch_critical_batch(const uint32_t *rec, const uint32_t *mask, int64_t n, const int64_t *foff,
+                          int nfields, const BatchField *fields, int64_t *const crit[4], const int64_t cap[4],
+                          int64_t *counts, int64_t *offsets, char *ws, uint32_t *flags, hipStream_t s)
 {
     (void)fields;
+    if (!mask) return DMS_E_ARG;
     const int64_t ntiles = (n + kTileRecs - 1) / kTileRecs;
     const int64_t len = 4 * ntiles + 1;
     const CritLayout L = crit_layout(ntiles);
     uint64_t *tc = (uint64_t *)ws;
     uint64_t *partials = (uint64_t *)(ws + L.partials);
-    hipLaunchKernelGGL(k_crit_count, dim3((unsigned)ntiles), dim3(kThreads), 0, s, (const uint4 *)rec,
-                       n, tc, ntiles, (uint16_t *)nullptr, (uint32_t *)nullptr);
+    const int64_t per_block = (int64_t)kWavesPerBlock * kTilesPerWave;
+    const unsigned blocks = (unsigned)((ntiles + per_block - 1) / per_block);
+    hipLaunchKernelGGL(k_crit_count_masked, dim3(blocks), dim3(kThreads), 0, s, (const uint4 *)rec, mask, n, tc,
+                       ntiles);
     exclusive_scan<uint64_t>(tc, len, partials, s);
-    const int64_t per_block = (int64_t)kWavesPerBlock * kBatchTilesPerWave;
-    hipLaunchKernelGGL(k_crit_fill_batch, dim3((unsigned)((ntiles + per_block - 1) / per_block)),
-                       dim3(kThreads), 0, s, (const uint4 *)rec, n, tc, ntiles, foff, nfields, crit[0],
-                       crit[1], crit[2], crit[3], cap[0], cap[1], cap[2], cap[3]);
+    hipLaunchKernelGGL(k_crit_fill_batch, dim3(blocks), dim3(kThreads), 0, s, (const uint4 *)rec, mask, n, tc,
+                       ntiles, foff, nfields, crit[0], crit[1], crit[2], crit[3], cap[0], cap[1], cap[2], cap[3]);
     hipLaunchKernelGGL(k_crit_fstart_batch, dim3((unsigned)nfields), dim3(kThreads), 0, s, (const uint4 *)rec,
                        tc, ntiles, foff, nfields, offsets);
     hipLaunchKernelGGL(k_crit_finish_batch, dim3(1), dim3(256), 0, s, tc, ntiles, nfields, offsets,

@@ -806,7 +806,8 @@ __global__ __launch_bounds__(kThreads, 8) void k_gradient_batch(const int32_t *_
                                                                 uint4 *__restrict__ rec,
                                                                 const uint4 *__restrict__ defect8,
                                                                 uint4 *__restrict__ queue,
-                                                                uint32_t *qcount, uint32_t qcap)
+                                                                uint32_t *qcount, uint32_t qcap,
+                                                                uint32_t *__restrict__ mark)
 {
     __shared__ BlockShared sh;
     __shared__ int32_t tile[Tile<GX, GY>::kHalo];
@@ -818,7 +819,7 @@ __global__ __launch_bounds__(kThreads, 8) void k_gradient_batch(const int32_t *_
     const int64_t k = t - tile_start[f];
     const int64_t bx = k % bxc, by = (k / bxc) % byc, bz = k / (bxc * byc);
     gradient_tile<RankKeys, GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1], F.n[2], bx,
-                                    by, bz, F.off, rec, defect8, queue, qcount, qcap, nullptr, nullptr, sh,
+                                    by, bz, F.off, rec, defect8, queue, qcount, qcap, nullptr, mark, sh,
                                     tile);
 }
 
@@ -1101,25 +1102,30 @@ int launch_gradient(int variant, const int32_t *order, const int64_t *dims, cons
 
 int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
                           const int64_t *tile_start, const uint16_t *tile_field, int64_t total_tiles,
-                          int64_t total_verts, uint32_t *rec, char *ws, hipStream_t s)
+                          int64_t total_verts, uint32_t *rec, uint32_t *mark, char *ws, hipStream_t s)
 {
     (void)nfields;
     if (total_tiles == 0) return DMS_OK;
     if (total_tiles > 2147483647LL) return DMS_E_SIZE;
+    if (mark) {
+        const int64_t words = (total_verts + 31) / 32;
+        hipLaunchKernelGGL(k_mark_zero, dim3((unsigned)((words + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                           mark, words);
+    }
     const uint4 *d8 = defect8_table();
     uint4 *queue;
     uint32_t *qcount, qcap;
     queue_begin(ws, total_verts, s, &queue, &qcount, &qcap);
 #define DMS_LAUNCH(GXV)                                                                               \
     hipLaunchKernelGGL((k_gradient_batch<GXV, kTileVerts / GXV>), dim3((unsigned)total_tiles), dim3(kThreads), \
-                       0, s, order, fields, tile_start, tile_field, (uint4 *)rec, d8, queue, qcount, qcap)
+                       0, s, order, fields, tile_start, tile_field, (uint4 *)rec, d8, queue, qcount, qcap, mark)
     switch (variant) {
     case 0: DMS_LAUNCH(64); break;
     case 1: DMS_LAUNCH(32); break;
     default: DMS_LAUNCH(16); break;
     }
 #undef DMS_LAUNCH
-    queue_finish(queue, qcount, qcap, rec, nullptr, s);
+    queue_finish(queue, qcount, qcap, rec, mark, s);
     return launch_status();
 }
 

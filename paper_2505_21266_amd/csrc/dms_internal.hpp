@@ -33,9 +33,10 @@ size_t gradient_workspace_size(int64_t owned);
 // a critical cell (zeroed here first).
 int launch_gradient(int variant, const int32_t *order, const int64_t *dims, const int64_t *lo,
                     const int64_t *hi, uint32_t *rec, uint32_t *mark, char *ws, hipStream_t s);
+// mark (may be null): as for launch_gradient, over the concatenated records.
 int launch_gradient_batch(int variant, const int32_t *order, const BatchField *fields, int nfields,
                           const int64_t *tile_start, const uint16_t *tile_field, int64_t total_tiles,
-                          int64_t total_verts, uint32_t *rec, char *ws, hipStream_t s);
+                          int64_t total_verts, uint32_t *rec, uint32_t *mark, char *ws, hipStream_t s);
 
 // Ranks of n 64-bit unsigned keys (rank[i] = position of key i in the
 // ascending stable sort), with the order passes.
@@ -56,11 +57,12 @@ size_t cell_rank_workspace_size(int64_t count);
 int launch_cell_ranks(const int64_t *codes, int64_t count, int dim, const int32_t *order, const int64_t *dims,
                       int32_t *rank, char *ws, uint32_t *flags, hipStream_t s);
 
-// Batched extraction over concatenated whole-field records.
+// Batched extraction over concatenated whole-field records; mask: the
+// critical mask launch_gradient_batch set (records it does not flag are
+// not read).
 size_t critical_batch_workspace_size(int64_t n, int nfields);
-int launch_critical_batch(const uint32_t *rec, int64_t n, const int64_t *foff, int nfields,
-                          const BatchField *fields, int64_t *const crit[4], const int64_t cap[4],
-                          int64_t *counts, int64_t *offsets, char *ws, uint32_t *flags,
-                          hipStream_t s);
+int launch_critical_batch(const uint32_t *rec, const uint32_t *mask, int64_t n, const int64_t *foff,
+                          int nfields, const BatchField *fields, int64_t *const crit[4], const int64_t cap[4],
+                          int64_t *counts, int64_t *offsets, char *ws, uint32_t *flags, hipStream_t s);
 
 }  // namespace dms
