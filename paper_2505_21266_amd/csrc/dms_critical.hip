@@ -595,17 +595,16 @@ __device__ __forceinline__ uint64_t emit_codes(uint32_t ce, uint64_t ct, uint32_
 // Masked extraction: the gradient set bit r of the mask for every record r
 // holding a critical cell, so the other records need not be read.  A wave
 // takes kTilesPerWave consecutive tiles, whose mask words it holds one per
-// lane.  When they flag at most kWave records (the usual case: most
-// vertices hold no critical cell), lane j takes the j-th flagged record and
-// one load serves the whole wave; otherwise the wave walks the tiles in rows
-// of kWave records (row k: words 2k and 2k + 1), skipping empty rows.  The
-// tiles' slots in the scanned counts are consecutive, so one running offset
-// serves both tiles.
-constexpr int kRows = kTileRecs / kWave;
+// lane, and their flagged records kWave at a time in record order: lane j
+// takes the chunk's j-th.  A smooth field flags few records (one chunk, one
+// load for the whole wave); a noise field flags about a quarter, most rows
+// of 64 records among them, so a walk by rows would read and decode nearly
+// all.  The tiles' slots in the scanned counts are consecutive, so one
+// running offset serves both tiles.
 constexpr int kTileWords = kTileRecs / 32;
 constexpr int kTilesPerWave = kWave / kTileWords;
 constexpr int kWavesPerBlock = kThreads / kWave;
-static_assert(kWave == 64 && kTileWords == 2 * kRows && kTilesPerWave == 2, "one mask word per lane");
+static_assert(kWave == 64 && kTilesPerWave == 2, "one mask word per lane");
 
 // The wave's flagged records: word = mask word `lane` of the wave's tiles.
 // flag_scan returns their number and sets inc (inclusive scan of the words'
@@ -634,26 +633,6 @@ __device__ __forceinline__ uint32_t flag_at(uint32_t word, uint32_t inc, uint32_
     return (uint32_t)w * 32u + select_bit(ww, j - before);
 }
 
-// Their number; when it is at most kWave, rel (of lane j < number) is the
-// j-th flagged record's position.
-__device__ __forceinline__ uint32_t list_flagged(uint32_t word, int lane, uint32_t &rel)
-{
-    uint32_t inc;
-    const uint32_t total = flag_scan(word, lane, inc);
-    rel = flag_at(word, inc, (uint32_t)lane < total ? (uint32_t)lane : 0u);
-    return total;
-}
-
-// Whether this lane's record of row k is flagged; row_empty when the row
-// flags none.
-__device__ __forceinline__ bool row_bit(uint32_t word, int k, int lane, bool &row_empty)
-{
-    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)word, 2 * k);
-    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)word, 2 * k + 1);
-    row_empty = (a | b) == 0u;
-    return ((lane < 32 ? a : b) >> (lane & 31)) & 1u;
-}
-
 __device__ __forceinline__ uint64_t count_record(const uint4 *__restrict__ rec, int64_t r, uint64_t &lo,
                                                  uint64_t &hi)
 {
@@ -680,20 +659,17 @@ __global__ __launch_bounds__(kThreads) void k_crit_count_masked(const uint4 *__r
     const int64_t wi = tile0 * kTileWords + lane;
     const uint32_t word = wi < (nbox + 31) / 32 ? mask[wi] : 0u;
     const int64_t r0 = tile0 * kTileRecs;
-    uint32_t rel;
-    const uint32_t total = list_flagged(word, lane, rel);
+    uint32_t inc;
+    const uint32_t total = flag_scan(word, lane, inc);
     uint64_t sum[kTilesPerWave] = {0, 0};
-    uint64_t lo, hi;
-    if (total <= (uint32_t)kWave) {
-        if ((uint32_t)lane < total && r0 + rel < nbox) sum[rel / kTileRecs] = count_record(rec, r0 + rel, lo, hi);
-    } else {
-#pragma unroll
-        for (int k = 0; k < kTilesPerWave * kRows; ++k) {
-            bool empty;
-            const bool flagged = row_bit(word, k, lane, empty);
-            if (empty) continue;
-            const int64_t r = r0 + k * kWave + lane;
-            if (flagged && r < nbox) sum[k / kRows] += count_record(rec, r, lo, hi);
+#pragma unroll 1
+    for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
+        const uint32_t j = c0 + (uint32_t)lane;
+        const uint32_t rel = flag_at(word, inc, j < total ? j : c0);  // every lane takes part in the shuffles
+        uint64_t lo, hi;
+        if (j < total && r0 + rel < nbox) {
+            const uint64_t pk = count_record(rec, r0 + rel, lo, hi);
+            if (rel < (uint32_t)kTileRecs) sum[0] += pk; else sum[1] += pk;
         }
     }
 #pragma unroll
@@ -727,22 +703,13 @@ __global__ __launch_bounds__(kThreads) void k_crit_fill_masked(
 #pragma unroll
     for (int d = 0; d < 4; ++d) at[d] = offs[(int64_t)d * ntiles + tile0] - offs[(int64_t)d * ntiles];
     const int64_t r0 = tile0 * kTileRecs;
-    uint32_t rel;
-    const uint32_t total = list_flagged(word, lane, rel);
-    const bool listed = total <= (uint32_t)kWave;
+    uint32_t inc;
+    const uint32_t total = flag_scan(word, lane, inc);
 #pragma unroll 1
-    for (int k = 0; k < (listed ? 1 : kTilesPerWave * kRows); ++k) {
-        int64_t r;
-        bool take;
-        if (listed) {
-            r = r0 + rel;
-            take = (uint32_t)lane < total;
-        } else {
-            bool empty;
-            take = row_bit(word, k, lane, empty);
-            if (empty) continue;
-            r = r0 + k * kWave + lane;
-        }
+    for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
+        const uint32_t j = c0 + (uint32_t)lane;
+        const bool take = j < total;
+        const int64_t r = r0 + flag_at(word, inc, take ? j : c0);
         uint64_t pk = 0;
         uint32_t ce = 0, cq = 0;
         uint64_t ct = 0;
