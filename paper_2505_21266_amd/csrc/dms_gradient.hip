@@ -786,8 +786,12 @@ __global__ __launch_bounds__(kThreads, 8) void k_gradient(const void *__restrict
     __shared__ BlockShared sh;
     __shared__ typename Keys::H tile[Tile<GX, GY>::kHalo];
     load_tables(sh.T);
-    const int64_t b = blockIdx.x;
-    const int64_t bx = b % bx_count, by = (b / bx_count) % by_count, bz = b / (bx_count * by_count);
+    // tiles in column order, z fastest: the tiles running at the same time
+    // then include each tile's neighbours above and below, which read two of
+    // its three halo planes, so most halo reads hit a cache (row order, with
+    // z slowest, put those neighbours a whole plane of tiles apart)
+    const int64_t t = blockIdx.x;
+    const int64_t bz = t % w2, col = t / w2, bx = col % bx_count, by = col / bx_count;
     gradient_tile<Keys, GX, GY>(field, nx, ny, nz, lo0, lo1, lo2, w0, w1, w2, bx, by, bz, 0, rec, defect8,
                                 queue, qcount, qcap, flags, mark, sh, tile);
 }
