@@ -820,8 +820,9 @@ __global__ __launch_bounds__(kThreads, 8) void k_gradient_batch(const int32_t *_
     const int f = tile_field[t];
     const BatchField F = fields[f];
     const int64_t bxc = (F.n[0] + GX - 1) / GX, byc = (F.n[1] + GY - 1) / GY;
+    // column order inside the field, as in k_gradient
     const int64_t k = t - tile_start[f];
-    const int64_t bx = k % bxc, by = (k / bxc) % byc, bz = k / (bxc * byc);
+    const int64_t bz = k % F.n[2], col = k / F.n[2], bx = col % bxc, by = col / bxc;
     gradient_tile<RankKeys, GX, GY>(order + F.off, F.n[0], F.n[1], F.n[2], 0, 0, 0, F.n[0], F.n[1], F.n[2], bx,
                                     by, bz, F.off, rec, defect8, queue, qcount, qcap, nullptr, mark, sh,
                                     tile);
