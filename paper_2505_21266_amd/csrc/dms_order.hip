@@ -29,7 +29,6 @@ namespace dms {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / kWave;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;
 constexpr int kRadix = 256;
@@ -71,9 +70,39 @@ __device__ __forceinline__ int field_of(const int64_t *foff, int nfields, int64_
     return field_between(foff, 0, nfields - 1, i);
 }
 
+// Coarse field table of a field pass, in LDS: entry j is the field of vertex
+// j << s (of the last vertex for entries past it), s being the smallest shift
+// that keeps the entries for [0, n) plus one within kFieldTable.  Vertex v's
+// field lies between entries v >> s and (v >> s) + 1: one or two fields unless
+// fields are shorter than 2^s vertices, in place of a search over all of them.
+constexpr int kFieldTable = 1024;
+
+__device__ __forceinline__ int field_table_shift(int64_t n)
+{
+    int s = 0;
+    while (((n - 1) >> s) + 2 > kFieldTable) ++s;
+    return s;
+}
+
+// The block fills tab from the LDS field offsets fo (n >= 1).
+__device__ __forceinline__ void build_field_table(uint16_t *tab, const int64_t *fo, int nfields, int64_t n, int s)
+{
+    const int64_t nent = ((n - 1) >> s) + 2;
+    for (int64_t j = threadIdx.x; j < nent; j += blockDim.x) {
+        const int64_t v = (j << s) < n ? (j << s) : n - 1;
+        tab[j] = (uint16_t)field_of(fo, nfields, v);
+    }
+}
+
+__device__ __forceinline__ int field_by_table(const uint16_t *tab, const int64_t *fo, int s, uint32_t v)
+{
+    const uint32_t j = v >> s;
+    return field_between(fo, tab[j], tab[j + 1], (int64_t)v);
+}
+
 // Batches of up to kFieldPassFields fields sort 4-byte value keys and then,
 // in a last pass, by the field of each vertex id, found in an LDS copy of the
-// field offsets (fo, nfields + 1 entries).
+// field offsets (fo, nfields + 1 entries) narrowed by a coarse table.
 constexpr int kFieldPassFields = 256;
 
 __device__ __forceinline__ void load_field_offsets(int64_t *fo, const int64_t *foff, int nfields)
@@ -177,6 +206,7 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
                                                         const int64_t *foff, int nfields)
 {
     __shared__ int64_t fo[kField ? kFieldPassFields + 1 : 1];
+    __shared__ uint16_t ftab[kField ? kFieldTable : 1];
     __shared__ HistRows hist;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const int64_t tile = tile_of_block(ntiles);
@@ -197,13 +227,18 @@ __global__ __launch_bounds__(kThr) void k_tile_hist(const void *src, int64_t n, 
     for (int i = tid; i < kCopies * (kRadix + 1); i += kThr) (&hist[0][0])[i] = 0;
     if constexpr (kField) load_field_offsets(fo, foff, nfields);
     __syncthreads();
+    const int fsh = kField ? field_table_shift(n) : 0;
+    if constexpr (kField) {
+        build_field_table(ftab, fo, nfields, n, fsh);
+        __syncthreads();
+    }
     bool nan_any = false;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const bool valid = local_index(wave, k, lane) < count;
         uint32_t d;
         if constexpr (kField) {
-            d = (uint32_t)field_of(fo, nfields, bid[k]);
+            d = (uint32_t)field_by_table(ftab, fo, fsh, bid[k]);
         } else {
             bool nan;
             const K key = to_key<V, K, kFirst>(raw[k], nan);
@@ -297,6 +332,7 @@ union Staging {
     } st;
     uint64_t ab[kThr * kItems];
     uint64_t mk[kThr / kWave][kRadix];
+    uint16_t ftab[kFieldTable];  // a field pass's coarse field table, while ranking by ballots
 };
 
 template <typename A, typename B>
@@ -538,12 +574,20 @@ __global__ __launch_bounds__(kThr) void k_scatter_last(const K *src, const uint3
             if constexpr (!kField) key[k] = src[at];  // the field pass needs only the ids
             id[k] = src_ids[at];
         }
+        // the field table lives in the staging bytes, unused until the
+        // ranking's barrier (the ranking matches by ballots, without the
+        // LDS masks)
+        const int fsh = kField ? field_table_shift(n) : 0;
+        if constexpr (kField) {
+            build_field_table(S.ftab, fo, nfields, n, fsh);
+            __syncthreads();
+        }
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const bool valid = local_index(wave, k, lane) < count;
             uint32_t d;
             if constexpr (kField)
-                d = (uint32_t)field_of(fo, nfields, id[k]);
+                d = (uint32_t)field_by_table(S.ftab, fo, fsh, id[k]);
             else
                 d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
             // the top byte (sign and exponent) takes few values, and a tile
