@@ -369,8 +369,8 @@ def bench_large(args, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the kernels work on one GPU's block); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
